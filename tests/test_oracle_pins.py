@@ -1,0 +1,405 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check is a closed form, a
+conservation law, a continuum limit, a library routine computing the same
+definition another way, or brute force.  CPU only.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+PI = math.pi
+
+
+# ---------------------------------------------------------------- kernels --
+
+@pytest.mark.parametrize("h", [0.3, 1.0, 2.5])
+def test_cubic_spline_normalised(orc, h):
+    # Sec. 2.2: the kernel integrates to one over space.
+    val, _ = integrate.quad(lambda r: 4 * PI * r * r * orc.W(r, h), 0, 2 * h, points=[h],
+                            epsabs=1e-13, epsrel=1e-13)
+    assert abs(val - 1.0) < 1e-10
+    assert orc.W(2 * h, h) == 0.0 and orc.W(2.5 * h, h) == 0.0   # compact support
+
+
+@pytest.mark.parametrize("h", [0.7, 1.3])
+def test_cubic_spline_smooth(orc, h):
+    # Continuity of W, W' and W'' at xi = 1 and of W, W' at xi = 2, and
+    # dW/dxi -> 0 as xi -> 0 (Sec. 2.2).  Together with the normalisation
+    # these fix the piecewise cubic uniquely.
+    f = lambda xi: orc.W(xi * h, h)
+    d = 1e-5
+    for xi0 in (1.0, 2.0):
+        assert abs(f(xi0 - 1e-9) - f(xi0 + 1e-9)) < 1e-7 / h ** 3
+        left = (f(xi0) - f(xi0 - d)) / d
+        right = (f(xi0 + d) - f(xi0)) / d
+        assert abs(left - right) < 1e-3 / h ** 3
+    l2 = (f(1 - 2 * d) - 2 * f(1 - d) + f(1)) / d ** 2
+    r2 = (f(1) - 2 * f(1 + d) + f(1 + 2 * d)) / d ** 2
+    assert abs(l2 - r2) < 1e-2 / h ** 3
+    assert abs((f(1e-6) - f(0)) / 1e-6) < 1e-4 / h ** 3
+    assert f(0.0) > f(0.5) > f(1.0) > f(1.5) > f(2.0) == 0.0
+
+
+@pytest.mark.parametrize("h", [0.4, 1.0, 3.0])
+def test_spiky_kernel_normalised_and_derivative(orc, h):
+    val, _ = integrate.quad(lambda r: 4 * PI * r * r * orc.Wp(r, h), 0, 2 * h,
+                            epsabs=1e-13, epsrel=1e-13)
+    assert abs(val - 1.0) < 1e-10
+    # dW_p/dxi must be the derivative of W_p with respect to xi = r/h.
+    for xi in (0.0, 0.3, 1.0, 1.7, 1.99):
+        d = 1e-6
+        num = (orc.Wp((xi + d) * h, h) - orc.Wp(max(xi - d, 0.0) * h, h)) / (xi + d - max(xi - d, 0.0))
+        assert abs(num - orc.dWp_dxi(xi * h, h)) < 1e-5 * abs(orc.dWp_dxi(0.0, h))
+    # non-zero slope at the origin: the reason the paper uses W_p for forces
+    assert orc.dWp_dxi(0.0, h) < 0.0
+    assert orc.dWp_dxi(2.0 * h, h) == 0.0
+
+
+# -------------------------------------------------------------- predicate --
+
+def test_predicate_ties_and_symmetry(orc):
+    # cut = h_i + h_j exactly representable: a pair at exactly that distance
+    # is not a neighbour (xi < 2 is strict), one ulp closer is.
+    p0 = (0.0, 0.0, 0.0)
+    assert not orc.pred(p0, 0.5, (1.0, 0.0, 0.0), 0.5)
+    assert orc.pred(p0, 0.5, (np.nextafter(np.float32(1.0), np.float32(0)).item(), 0.0, 0.0), 0.5)
+    assert not orc.pred(p0, 0.25, (0.0, 0.0, 0.5), 0.25)
+    assert not orc.pred(p0, 0.5, (0.0, 0.0, 0.0 + 1.0), 0.5)
+    rng = np.random.default_rng(1)
+    for _ in range(2000):
+        a = rng.normal(size=3) * 3
+        b = a + rng.normal(size=3) * 0.3
+        ha, hb = rng.uniform(0.01, 0.3, 2)
+        assert orc.pred(a, ha, b, hb) == orc.pred(b, hb, a, ha)
+
+
+def test_predicate_matches_geometry_away_from_boundary(orc):
+    # Away from |r| = h_i + h_j the FP32 test equals the exact FP64 geometry.
+    rng = np.random.default_rng(2)
+    n_checked = 0
+    for _ in range(5000):
+        a = rng.uniform(-10, 10, 3)
+        b = a + rng.normal(size=3) * 0.2
+        ha, hb = rng.uniform(0.01, 0.2, 2)
+        r = np.linalg.norm(a - b)
+        if abs(r - (ha + hb)) < 1e-5 * (ha + hb):
+            continue
+        n_checked += 1
+        assert orc.pred(a, ha, b, hb) == (r < ha + hb)
+    assert n_checked > 4900
+
+
+# ------------------------------------------------------- grid, sort, rows --
+
+def _clustered(rng, n):
+    """Dense core + sparse envelope + exact duplicates: variable h over ~20x."""
+    r = rng.pareto(2.5, n) * 0.3
+    u = rng.normal(size=(n, 3))
+    pos = u / np.linalg.norm(u, axis=1)[:, None] * r[:, None]
+    pos[n // 10: n // 10 + 20] = pos[0]          # coincident particles
+    h = 0.02 + 0.08 * r + rng.uniform(0, 0.01, n)
+    return pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), h
+
+
+def test_grid_rule_properties(orc):
+    rng = np.random.default_rng(3)
+    x, y, z, h = _clustered(rng, 3000)
+    g = orc.grid(x, y, z, h)
+    gd = orc.grid_dict(g)
+    key, lev = orc.keys(x, y, z, h, g)
+    t = h * (2.0 + 2.0 ** -9)
+    L0 = gd["L0"]
+    assert math.frexp(L0)[0] == 0.5                          # power of two
+    assert L0 >= t.min() and L0 / 2 < t.min()
+    L = L0 * 2.0 ** lev
+    assert np.all(L >= t)
+    assert np.all((lev == 0) | (L / 2 < t))                   # first level that fits
+    # every particle lies inside its cell
+    for l in range(gd["nlev"]):
+        sel = lev == l
+        if not sel.any():
+            assert gd["ncell"][l] == 0
+            continue
+        Ll, o, dim, base = gd["L"][l], gd["org"][l], gd["dim"][l], gd["base"][l]
+        loc = key[sel].astype(np.int64) - base
+        cx = loc % dim[0]
+        cy = (loc // dim[0]) % dim[1]
+        cz = loc // (dim[0] * dim[1])
+        for c, p, d in ((cx, x[sel], 0), (cy, y[sel], 1), (cz, z[sel], 2)):
+            assert np.all(o[d] + c * Ll <= p) and np.all(p < o[d] + (c + 1) * Ll)
+            assert np.all((c >= 0) & (c < dim[d]))
+        assert np.all(loc < gd["ncell"][l])
+    assert gd["M"] == gd["ncell"].sum()
+
+
+def test_counting_sort_matches_library(orc):
+    rng = np.random.default_rng(4)
+    x, y, z, h = _clustered(rng, 5000)
+    s = orc.sort_gas(x, y, z, h)
+    M = s["grid"].M
+    np.testing.assert_array_equal(s["count"], np.bincount(s["key"], minlength=M))
+    np.testing.assert_array_equal(s["off"], np.concatenate([[0], np.cumsum(s["count"])]))
+    np.testing.assert_array_equal(s["perm"], np.argsort(s["key"], kind="stable"))
+    hm = np.zeros(M)
+    np.maximum.at(hm, s["key"], h)
+    np.testing.assert_array_equal(s["hmax"], hm)
+
+
+def test_neighbour_rows_two_methods_agree(orc):
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 50, 3000):
+        x, y, z, h = _clustered(rng, max(n, 30))
+        x, y, z, h = x[:n], y[:n], z[:n], h[:n]
+        a = orc.nbrs_brute(x, y, z, h)
+        b = orc.nbrs_kdtree(x, y, z, h)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        off, idx = a
+        rows = [set(idx[off[i]:off[i + 1]].tolist()) for i in range(n)]
+        for i in range(n):
+            r = idx[off[i]:off[i + 1]]
+            assert i not in rows[i]
+            assert np.all(np.diff(r) > 0)
+            for j in r:
+                assert i in rows[j]                                  # symmetric
+
+
+def test_slot_rows(orc):
+    rng = np.random.default_rng(6)
+    x, y, z, h = _clustered(rng, 1500)
+    s = orc.sort_gas(x, y, z, h)
+    off, idx = orc.nbrs_brute(x, y, z, h)
+    soff, sidx = orc.rows_to_slots(s["perm"], off, idx)
+    perm = s["perm"]
+    for sl in range(0, 1500, 7):
+        got = perm[sidx[soff[sl]:soff[sl + 1]]]
+        exp = idx[off[perm[sl]]:off[perm[sl] + 1]]
+        np.testing.assert_array_equal(np.sort(got), exp)
+        assert np.all(np.diff(sidx[soff[sl]:soff[sl + 1]]) > 0)
+
+
+# ------------------------------------------------------------------ SPH ----
+
+def _lattice(n, d):
+    g = np.arange(n) * d
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    return X.ravel().copy(), Y.ravel().copy(), Z.ravel().copy()
+
+
+@pytest.mark.parametrize("hd,tol", [(1.2, 2e-3), (1.5, 3e-3), (2.0, 3e-4)])
+def test_lattice_density_normalisation(orc, hd, tol):
+    # Uniform lattice of spacing d and particle mass m: the SPH density of an
+    # interior particle (Eq. SPH-mass-density, self term included) tends to
+    # m/d^3 as h/d grows, by the kernel's normalisation.  Dropping the self
+    # term, using h_i + h_j instead of the mean, or a wrong kernel constant
+    # each moves it by > 5%.
+    n, d = 13, 0.1
+    x, y, z = _lattice(n, d)
+    N = len(x)
+    m = np.full(N, 2.0 * d ** 3)
+    h = np.full(N, hd * d)
+    off, idx = orc.nbrs_brute(x, y, z, h)
+    rho = orc.density(x, y, z, m, h, off, idx)
+    c = (n // 2) * n * n + (n // 2) * n + n // 2
+    assert abs(rho[c] / 2.0 - 1.0) < tol
+
+
+@pytest.mark.parametrize("hd,tol", [(1.5, 0.025), (2.0, 0.006)])
+def test_lattice_pressure_gradient_limit(orc, hd, tol):
+    # Eq. (dv_dt): a = -grad p / rho.  Uniform density, e linear in x, so
+    # p = (gamma-1) rho e has gradient (gamma-1) rho k along x: the SPH sum of
+    # Eq. (dv_dt-SPH) must approach -(gamma-1) k at an interior particle.
+    # Pins the sign, the W_p normalisation, the 1/h_ij of grad W_p.
+    n, d, gam, k = 14, 0.1, 5.0 / 3.0, 0.3
+    x, y, z = _lattice(n, d)
+    N = len(x)
+    m = np.full(N, d ** 3)
+    h = np.full(N, hd * d)
+    off, idx = orc.nbrs_brute(x, y, z, h)
+    rho = orc.density(x, y, z, m, h, off, idx)
+    zero = np.zeros(N)
+    ax, ay, az, de = orc.sph_force(x, y, z, zero, zero, zero, m, h, rho, 1.0 + k * x,
+                                   gam, 1.0, 2.0, 0.1, off, idx)
+    c = (n // 2) * n * n + (n // 2) * n + n // 2
+    expect = -(gam - 1) * k
+    assert abs(ax[c] / expect - 1) < tol
+    assert abs(ay[c]) < 1e-12 and abs(az[c]) < 1e-12
+
+
+@pytest.mark.parametrize("hd,tol", [(1.5, 0.025), (2.0, 0.006)])
+def test_lattice_divergence_limit(orc, hd, tol):
+    # Eq. (de_dt): de/dt = -(p/rho) div v.  Uniform expansion v = c r has
+    # div v = 3c and r.v > 0 for every pair, so the viscosity is off and
+    # Eq. (de_dt-SPH) must approach -3 c p / rho.  Pins the 1/2 and the sign.
+    n, d, gam, cdiv = 14, 0.1, 5.0 / 3.0, 0.2
+    x, y, z = _lattice(n, d)
+    N = len(x)
+    m = np.full(N, d ** 3)
+    h = np.full(N, hd * d)
+    off, idx = orc.nbrs_brute(x, y, z, h)
+    rho = orc.density(x, y, z, m, h, off, idx)
+    e = np.ones(N)
+    ax, ay, az, de = orc.sph_force(x, y, z, cdiv * x, cdiv * y, cdiv * z, m, h, rho, e,
+                                   gam, 1.0, 2.0, 0.1, off, idx)
+    c = (n // 2) * n * n + (n // 2) * n + n // 2
+    p = (gam - 1) * rho[c] * e[c]
+    assert abs(de[c] / (-3 * cdiv * p / rho[c]) - 1) < tol
+    # compression heats, and viscosity adds to the heating
+    ax2, _, _, de2 = orc.sph_force(x, y, z, -cdiv * x, -cdiv * y, -cdiv * z, m, h, rho, e,
+                                   gam, 0.0, 0.0, 0.1, off, idx)
+    ax3, _, _, de3 = orc.sph_force(x, y, z, -cdiv * x, -cdiv * y, -cdiv * z, m, h, rho, e,
+                                   gam, 1.0, 2.0, 0.1, off, idx)
+    assert abs(de2[c] / (3 * cdiv * p / rho[c]) - 1) < tol
+    assert de3[c] > de2[c] > 0
+
+
+def _gas_blob(rng, n):
+    x, y, z, h = _clustered(rng, n)
+    m = rng.uniform(0.5, 1.5, n) / n
+    v = rng.normal(size=(n, 3)) * 0.3
+    e = rng.uniform(0.02, 0.1, n)
+    return x, y, z, v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy(), m, h, e
+
+
+def test_sph_conservation_laws(orc):
+    # Pi_ij symmetric and grad W_p antisymmetric: total momentum and angular
+    # momentum are conserved exactly, and sum m (v.a + de/dt) = 0 pins the
+    # 1/2 of Eq. (de_dt-SPH) against the momentum equation.
+    rng = np.random.default_rng(7)
+    x, y, z, vx, vy, vz, m, h, e = _gas_blob(rng, 2000)
+    off, idx = orc.nbrs_brute(x, y, z, h)
+    rho = orc.density(x, y, z, m, h, off, idx)
+    ax, ay, az, de = orc.sph_force(x, y, z, vx, vy, vz, m, h, rho, e, 5 / 3, 1.0, 2.0, 0.1, off, idx)
+    scale = np.sum(m * np.sqrt(ax ** 2 + ay ** 2 + az ** 2))
+    for comp in (ax, ay, az):
+        assert abs(np.sum(m * comp)) < 1e-12 * scale
+    r = np.stack([x, y, z], 1)
+    a = np.stack([ax, ay, az], 1)
+    Lz = np.sum(m[:, None] * np.cross(r, a), axis=0)
+    assert np.all(np.abs(Lz) < 1e-12 * np.sum(m * np.linalg.norm(r, axis=1) * np.linalg.norm(a, axis=1)))
+    work = m * (vx * ax + vy * ay + vz * az)
+    heat = m * de
+    assert abs(np.sum(work + heat)) < 1e-11 * (np.sum(np.abs(work)) + np.sum(np.abs(heat)))
+    # Galilean invariance
+    ax2, ay2, az2, de2 = orc.sph_force(x, y, z, vx + 3.0, vy - 1.0, vz, m, h, rho, e,
+                                       5 / 3, 1.0, 2.0, 0.1, off, idx)
+    np.testing.assert_allclose(ax2, ax, rtol=1e-9, atol=1e-12 * np.abs(ax).max())
+    np.testing.assert_allclose(de2, de, rtol=1e-9, atol=1e-12 * np.abs(de).max())
+
+
+def test_viscosity_scaling(orc):
+    # nu = mu (beta mu - alpha c)/rho_ij: the alpha part of the heating is
+    # linear in alpha and the beta part scales as |v|^3 (mu ~ v, mu^2 dv ~ v^3).
+    rng = np.random.default_rng(8)
+    x, y, z, vx, vy, vz, m, h, e = _gas_blob(rng, 800)
+    off, idx = orc.nbrs_brute(x, y, z, h)
+    rho = orc.density(x, y, z, m, h, off, idx)
+
+    def heat(a, b, s):
+        return orc.sph_force(x, y, z, s * vx, s * vy, s * vz, m, h, rho, e, 5 / 3, a, b, 0.1,
+                             off, idx)[3]
+    base1 = heat(0, 0, 1.0)
+    da1 = heat(1, 0, 1.0) - base1
+    da2 = heat(2, 0, 1.0) - base1
+    np.testing.assert_allclose(da2, 2 * da1, rtol=1e-9, atol=1e-14)
+    db1 = heat(0, 1, 1.0) - base1
+    base2 = heat(0, 0, 2.0)
+    db2 = heat(0, 1, 2.0) - base2
+    np.testing.assert_allclose(db2, 8 * db1, rtol=1e-9, atol=1e-14)
+    assert np.sum(m * da1) > 0 and np.sum(m * db1) > 0          # dissipative
+
+
+# -------------------------------------------------------------- gravity ----
+
+def test_gravity_two_body_closed_form(orc):
+    G, eps = 1.7, 0.05
+    x = np.array([0.0, 0.6]); y = np.zeros(2); z = np.zeros(2)
+    m = np.array([2.0, 3.0])
+    ax, ay, az, pot = orc.gravity(x, y, z, m, G, eps)
+    d2 = 0.36 + eps * eps
+    assert abs(ax[0] - G * 3.0 * 0.6 / d2 ** 1.5) < 1e-14
+    assert abs(ax[1] + G * 2.0 * 0.6 / d2 ** 1.5) < 1e-14
+    assert abs(pot[0] + G * 3.0 / math.sqrt(d2)) < 1e-14
+    assert ay[0] == 0 and az[1] == 0
+
+
+def test_gravity_newton_third_law(orc):
+    rng = np.random.default_rng(9)
+    n = 3000
+    x, y, z = rng.normal(size=(3, n))
+    m = rng.uniform(0.1, 1.0, n)
+    ax, ay, az, pot = orc.gravity(x, y, z, m, 1.0, 0.01)
+    for comp in (ax, ay, az):
+        assert abs(np.sum(m * comp)) < 1e-13 * np.sum(m * np.abs(comp))
+    r = np.stack([x, y, z], 1)
+    a = np.stack([ax, ay, az], 1)
+    L = np.sum(m[:, None] * np.cross(r, a), axis=0)
+    assert np.all(np.abs(L) < 1e-13 * np.sum(m * np.linalg.norm(r, 1) * np.linalg.norm(a, 1)))
+    # subset evaluation agrees with the full one
+    t = np.array([5, 17, 2999, 0])
+    bx, by, bz, bp = orc.gravity(x, y, z, m, 1.0, 0.01, targets=t)
+    np.testing.assert_array_equal(bx, ax[t])
+    np.testing.assert_array_equal(bp, pot[t])
+
+
+def _plummer_menc(r, a, rt):
+    X = lambda s: s ** 3 / (s * s + a * a) ** 1.5
+    return np.minimum(X(r), X(rt)) / X(rt)
+
+
+def test_gravity_plummer_profile(orc):
+    # Radial field of a sampled (truncated) Plummer sphere against
+    # -G M(<r)/r^2 in radial shells: statistical, softening O(eps^2).
+    from paper_1807_08116_amd import ic
+    rng = np.random.default_rng(10)
+    pos, m = ic.plummer(12000, 1.0, 1.0, rng)
+    x, y, z = pos.T.copy()
+    ax, ay, az, pot = orc.gravity(x, y, z, m, 1.0, 0.01)
+    r = np.linalg.norm(pos, axis=1)
+    ar = (ax * x + ay * y + az * z) / r
+    for lo, hi in ((0.3, 0.6), (0.6, 1.0), (1.0, 1.6), (1.6, 3.0)):
+        sel = (r > lo) & (r < hi)
+        ratio = np.mean(-ar[sel] * r[sel] ** 2 / _plummer_menc(r[sel], 1.0, 5.0))
+        assert abs(ratio - 1) < 0.03, (lo, hi, ratio)
+    # potential energy of the truncated sphere: -G int M(r) dM(r) / r
+    rt = 5.0
+    Xt = rt ** 3 / (rt * rt + 1.0) ** 1.5          # Plummer mass fraction inside rt
+    dens = lambda s: 3.0 / (4 * PI) * (1 + s * s) ** -2.5 / Xt
+    Wint, _ = integrate.quad(lambda s: -_plummer_menc(s, 1.0, rt) * 4 * PI * s * dens(s), 0, rt)
+    Wsim = 0.5 * np.sum(m * pot)
+    assert abs(Wsim / Wint - 1) < 0.02
+
+
+# ----------------------------------------------------------- integrator ----
+
+def test_predictor_corrector_second_order_kepler(orc):
+    # Halo-only eccentric two-body orbit: the scheme is second order in dt
+    # (Sec. 2.2), so the position error at a fixed time falls ~4x when dt
+    # halves (reference: the same scheme at a 32x smaller step).
+    prm = dict(G=1.0, eps=1e-4, gamma=5 / 3, alpha=1, beta=2, eta=0.1)
+
+    def run(dt, t_end=1.2):
+        v = 0.35                       # below the circular speed 0.5: eccentric
+        st = {"ng": 0, "x": np.array([-0.5, 0.5]), "y": np.zeros(2), "z": np.zeros(2),
+              "vx": np.zeros(2), "vy": np.array([-v, v]), "vz": np.zeros(2),
+              "m": np.array([0.5, 0.5]), "e": np.zeros(0), "h": np.zeros(0)}
+        cache = None
+        for _ in range(int(round(t_end / dt))):
+            st, cache = orc.pc_step(st, prm, dt, cache)
+        return np.array([st["x"][1], st["y"][1]])
+    ref = run(0.02 / 32)
+    e_a = np.linalg.norm(run(0.02) - ref)
+    e_b = np.linalg.norm(run(0.01) - ref)
+    assert 3.3 < e_a / e_b < 4.7, e_a / e_b
+
+
+def test_diagnostics_closed_form(orc):
+    x = np.array([1.0, -1.0]); y = np.zeros(2); z = np.zeros(2)
+    vx = np.zeros(2); vy = np.array([1.0, -1.0]); vz = np.zeros(2)
+    m = np.array([1.0, 1.0]); e = np.array([0.25])
+    pot = np.array([-0.5, -0.5])
+    d = orc.diagnostics(x, y, z, vx, vy, vz, m, e, pot, 1)
+    np.testing.assert_allclose(d, [1.0, 0.25, -0.5, 0.75, 0, 0, 0, 0, 0, 2.0], atol=1e-15)
