@@ -1,0 +1,209 @@
+"""Benchmark: force-steps/s of the SPH + direct-gravity step at 2M particles.
+
+One step = one predictor-corrector step of the paper's scheme (neighbour
+build, density, gravity once, SPH forces twice, two updates) plus the FP64
+conserved-quantity reduction, over the head-on collision of two Plummer
+gas+halo systems, 1048576 gas + 1048576 halo particles (synthetic, seeded).
+
+The headline value is the FP32-compensated form's steps/s; the FP64 form is
+timed beside it, and both forms' acceleration error against the FP64 CPU
+oracle on a seeded 4096-particle subset is reported.  The gravity pair
+kernel (the dominant kernel) is timed with HIP events on the library's
+stream for the roofline figure.  The oracle is timed on the host on a
+bounded sample (gravity of the 4096-particle subset plus the whole SPH part)
+and extrapolated to one step.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = 22          # 20 for the acceleration, +2 for the potential
+PEAK = {"fp32": 157.3, "fp64": 78.6}  # TFLOP/s, MI355X vector peaks
+DT = 1e-3
+
+
+def nrm_err(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(sg, st, precision, steps, warmup, sample):
+    import torch
+    eng = sg.Engine(st, precision=precision)
+    ctx = eng.ctx
+    # force evaluation at t = 0 (for the error check against the oracle)
+    eng.build_neighbors()
+    ctx.compute_density()
+    ctx.compute_accel(sg.SG_SPH | sg.SG_GRAV | sg.SG_POT)
+    ctx.sync()
+    acc = np.stack([eng.dev[f][sample].cpu().numpy() for f in ("ax", "ay", "az")], 1)
+    diag = ctx.diagnostics()
+    for _ in range(warmup):
+        ctx.step(DT, sg.SG_POT)
+        ctx.diagnostics(diag)
+    ctx.sync()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(DT, sg.SG_POT)
+        ctx.diagnostics(diag)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    ctx.sync()
+    d = diag.cpu().numpy()
+    eng.ctx.close()
+    del eng
+    torch.cuda.empty_cache()
+    return {"sec": (t1 - t0), "acc": acc, "prof": prof, "diag": d.tolist()}
+
+
+def cpu_baseline(st, sample, prm):
+    """Time the oracle on a bounded sample of the same workload."""
+    import oracle
+    oracle.lib()
+    ng = st["ng"]
+    n = len(st["x"])
+    x, y, z = st["x"][:ng], st["y"][:ng], st["z"][:ng]
+    t = time.perf_counter()
+    oracle.sort_gas(x, y, z, st["h"])
+    nb = oracle.nbrs(x, y, z, st["h"])
+    t_nbr = time.perf_counter() - t
+    t = time.perf_counter()
+    rho = oracle.density(x, y, z, st["m"][:ng], st["h"], *nb)
+    t_dens = time.perf_counter() - t
+    t = time.perf_counter()
+    asx, asy, asz, de = oracle.sph_force(x, y, z, st["vx"][:ng], st["vy"][:ng], st["vz"][:ng],
+                                         st["m"][:ng], st["h"], rho, st["e"], prm["gamma"],
+                                         prm["alpha"], prm["beta"], prm["eta"], *nb)
+    t_sph = time.perf_counter() - t
+    t = time.perf_counter()
+    gx, gy, gz, gp = oracle.gravity(st["x"], st["y"], st["z"], st["m"], prm["G"], prm["eps"],
+                                    sample)
+    t_grav = time.perf_counter() - t
+    ref = np.stack([gx, gy, gz], 1)
+    gas = sample < ng
+    ref[gas, 0] += asx[sample[gas]]
+    ref[gas, 1] += asy[sample[gas]]
+    ref[gas, 2] += asz[sample[gas]]
+    step_s = t_nbr + t_dens + 2 * t_sph + t_grav * n / len(sample)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        cores = min(cores, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        pass
+    return ref, {
+        "value": 1.0 / step_s, "unit": "force-steps/s", "cores": cores, "kind": "oracle",
+        "sample": ("gravity of %d seeded targets over all %d sources (x%.0f to a step) + whole "
+                   "SPH part (neighbours %.1fs, density %.1fs, forces %.1fs x2); gravity %.1fs"
+                   % (len(sample), n, n / len(sample), t_nbr, t_dens, t_sph, t_grav)),
+        "extrapolated": True,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--only", choices=["fp32c", "fp64", "both"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_1807_08116_amd import ic
+    from paper_1807_08116_amd import sphgrav as sg
+    sg.lib()
+    prm = ic.DEFAULT_PARAMS
+    t = time.perf_counter()
+    st = ic.make(args.config)
+    n, ng = len(st["x"]), st["ng"]
+    log("inputs %s: N=%d (gas %d) in %.1fs" % (args.config, n, ng, time.perf_counter() - t))
+    sample = np.sort(np.random.default_rng(ic.SEED_BASE + 99).choice(n, 4096, replace=False))
+
+    res = {}
+    forms = ["fp32c", "fp64"] if args.only == "both" else [args.only]
+    for form in forms:
+        p = sg.SG_FP32C if form == "fp32c" else sg.SG_FP64
+        log("timing %s: %d warmup + %d steps" % (form, args.warmup, args.steps))
+        res[form] = run_form(sg, st, p, args.steps, args.warmup, sample)
+        log("  %s: %.3f s/step" % (form, res[form]["sec"] / args.steps))
+
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        log("oracle baseline on the host ...")
+        ref, cpu = cpu_baseline(st, sample, prm)
+        for form in forms:
+            errs[form] = nrm_err(res[form]["acc"], ref)
+        log("  oracle %.4g steps/s (extrapolated); errors %s" % (cpu["value"], errs))
+
+    head = "fp32c" if "fp32c" in res else "fp64"
+    sec = res[head]["sec"]
+    gms, glaunch = res[head]["prof"]["grav"]
+    grav_s = gms / 1e3 / max(glaunch, 1)
+    achieved = FLOPS_PER_PAIR * float(n) * float(n) / grav_s / 1e12
+    peak = PEAK["fp32" if head == "fp32c" else "fp64"]
+    out = {
+        "metric": "force-steps/s at 2M particles, FP32-compensated vs FP64, at 1e-6 accel err",
+        "value": args.steps / sec,
+        "unit": "force-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32c" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: head-on collision of two Plummer gas+halo systems, "
+                               "%d gas + %d halo particles, one predictor-corrector step "
+                               "+ FP64 energy/momentum sums" % (args.config, ng, n - ng),
+                   "n_particles": n, "n_gas": ng, "precision_form": head, "seed": ic.SEED_BASE + int(args.config[1:])},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "gravity pair kernel (%s), %d flops/pair x N^2 per launch, "
+                               "%.1f ms/launch" % (head, FLOPS_PER_PAIR, 1e3 * grav_s)},
+        "cpu_baseline": cpu,
+        "accel_err_vs_oracle": errs,
+        "pairs_per_s": float(n) * n / grav_s,
+    }
+    for form in res:
+        pr = res[form]["prof"]
+        out[form] = {
+            "steps_per_s": args.steps / res[form]["sec"],
+            "ms_per_step": 1e3 * res[form]["sec"] / args.steps,
+            "stage_ms_per_step": {k: v[0] / args.steps for k, v in pr.items()},
+            "grav_ms_per_launch": pr["grav"][0] / max(pr["grav"][1], 1),
+            "accel_err": errs.get(form),
+            "diagnostics_last": res[form]["diag"],
+        }
+    if "fp64" in res and "fp32c" in res:
+        out["fp32c_vs_fp64_speedup"] = res["fp64"]["sec"] / res["fp32c"]["sec"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * sphgrav.h -- C ABI of libsphgrav.so: the per-timestep force evaluation of
+ * self-gravitating SPH with direct (Particle-Particle) gravity, after
+ * Khrapov & Khoperskov, "Smoothed-Particle Hydrodynamics Models:
+ * Implementation Features on GPUs" (CCIS 793, 2017), on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Particles: N = N_g + N_h (Sec. 2.1).  Gas (SPH) particles occupy indices
+ *   [0, N_g), collisionless halo particles [N_g, N).
+ * - Memory: every buffer handed to the library is DEVICE memory owned by the
+ *   caller, laid out as structure-of-arrays of FP64.  The library never
+ *   allocates or frees device memory: its scratch lives in one caller-owned
+ *   workspace blob sized by sg_workspace_bytes().  Host-side it allocates
+ *   only the small opaque context.
+ * - Streams: all work is enqueued on the HIP stream given to sg_create();
+ *   entry points return as soon as the work is enqueued.  Only
+ *   sg_sync() and sg_export() wait for the stream.
+ * - Errors: every call returns an sg_status; nothing aborts and no C++
+ *   exception crosses the ABI.  Argument errors are detected on the host
+ *   before any HIP call.  Conditions only the device can see (capacity
+ *   overflow, bad smoothing lengths, non-finite positions) are latched in
+ *   a device error word: the affected kernels then do nothing, and the
+ *   next sg_sync() reports the condition and the capacity required.
+ * - Threading: one context per stream; a context is not thread-safe.
+ * - Indices are int32 (N < 2^31); CSR offsets are int64.
+ */
+#ifndef SPHGRAV_H
+#define SPHGRAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SG_OK = 0,
+    SG_EINVAL = 1,      /* bad argument (null pointer, size, parameter)        */
+    SG_ECAPACITY = 2,   /* a device capacity (cells, neighbour pairs) was too small */
+    SG_EDEVICE = 3,     /* a HIP runtime call failed                           */
+    SG_ESTATE = 4,      /* call out of order (e.g. density before neighbours)  */
+    SG_ENONFINITE = 5,  /* non-finite position or non-positive/non-finite h    */
+    SG_ERANGE = 6       /* smoothing lengths span more than SG_MAX_LEVELS levels */
+} sg_status;
+
+typedef enum {
+    SG_FP64 = 0,        /* all pair arithmetic and sums in FP64                 */
+    SG_FP32C = 1        /* FP32 pair arithmetic on anchor-relative coordinates,
+                           Kahan-compensated FP32 partial sums; FP64 state,
+                           update (drift/kick) and reductions                  */
+} sg_precision;
+
+/* Flags of sg_compute_accel() / sg_step(). */
+#define SG_SPH  1u      /* hydrodynamic acceleration and de/dt (Eqs. dv_dt-SPH, de_dt-SPH) */
+#define SG_GRAV 2u      /* direct gravity (Eq. self-gravity)                      */
+#define SG_POT  4u      /* also the gravitational potential (needs SG_GRAV)       */
+
+/* Phases of sg_kick_drift(). */
+#define SG_PREDICT 0
+#define SG_CORRECT 1
+
+#define SG_MAX_LEVELS 16
+
+/* Physical and tuning parameters.
+ * G, eps: gravitational constant and Plummer softening length; the
+ *   paper's softened pair force (Eq. self-gravity, whose printed
+ *   denominator is read as (|r_ij|^2 + eps^2)^{3/2}); eps must be > 0.
+ * gamma: adiabatic index of the ideal-gas law (Eq. e_p_rho), > 1.
+ * alpha, beta, eta: artificial-viscosity constants (Sec. 2.2), >= 0, eta > 0.
+ * precision: an sg_precision value.
+ * grav_ipl: target particles per GPU lane in the gravity kernel (1, 2 or 4;
+ *   0 = automatic).  grav_split: number of source-range splits (>= 1;
+ *   0 = automatic).  Neither changes results beyond summation order. */
+typedef struct {
+    double G, eps, gamma, alpha, beta, eta;
+    int32_t precision;
+    int32_t grav_ipl;
+    int32_t grav_split;
+    int32_t reserved[5];        /* must be zero */
+} sg_params;
+
+/* Capacities the workspace is sized for.
+ * n_gas_cap, n_halo_cap: maximum N_g and N_h of any bound state.
+ * cell_cap: maximum number of grid cells M (sum over levels).
+ * nnz_cap: maximum number of (ordered) neighbour pairs. */
+typedef struct {
+    int64_t n_gas_cap, n_halo_cap, cell_cap, nnz_cap;
+} sg_caps;
+
+/* Device pointers of the particle state (caller-owned, FP64, SoA).
+ * Inputs/updated state: x,y,z,vx,vy,vz,m [N]; h,e [N_g].
+ * Outputs: ax,ay,az [N] total acceleration (SPH + gravity for gas, gravity
+ * for halo), dedt [N_g], rho [N_g]; pot [N] may be NULL unless SG_POT is
+ * requested. */
+typedef struct {
+    double *x, *y, *z, *vx, *vy, *vz, *m;
+    double *h, *e;
+    double *ax, *ay, *az;
+    double *dedt, *rho;
+    double *pot;
+} sg_state;
+
+typedef struct sg_ctx sg_ctx;   /* opaque */
+
+/* Bytes of device workspace needed for these parameters and capacities.
+ * Returns 0 if the arguments are invalid. */
+size_t sg_workspace_bytes(const sg_params *prm, const sg_caps *caps);
+
+/* Create a context over a caller-owned workspace of ws_bytes bytes
+ * (>= sg_workspace_bytes, 256-byte aligned) on HIP stream `stream`
+ * (a hipStream_t; NULL = the default stream).  The workspace must stay
+ * allocated until sg_destroy().  Enqueues a clear of the device status. */
+sg_status sg_create(const sg_params *prm, const sg_caps *caps, void *d_workspace,
+                    size_t ws_bytes, void *stream, sg_ctx **out);
+
+/* Bind a particle state (the "upload" step: the state already sits in
+ * device memory owned by the caller).  n_gas <= n_gas_cap, n_halo <=
+ * n_halo_cap, n_gas + n_halo >= 1.  Invalidates cached neighbours, density
+ * and forces. */
+sg_status sg_bind_state(sg_ctx *ctx, int64_t n_gas, int64_t n_halo, const sg_state *st);
+
+/* Grid sort and neighbour lists of the gas at the current positions
+ * (Sec. 3, kernels SP): smoothing-length levels and grid parameters, cell
+ * keys, per-cell counts and maximum h, prefix sums for cell offsets,
+ * stable particle reorder (ascending particle id inside a cell), and a CSR
+ * list, by sorted slot, of every other gas particle j with xi_ij < 2, i.e.
+ * |r_ij| < h_i + h_j.  The test is done in FP32 so that lists are exact and
+ * reproducible: d = (float)(r_i - r_j) per component (FP64 difference
+ * rounded once), r2 = fmaf(dz,dz, fmaf(dy,dy, dx*dx)),
+ * c = (float)h_i + (float)h_j, neighbour iff r2 < c*c.
+ * Grid: levels l = 0,1,.. of cubic cells of side L_l = L_0 2^l, L_0 the
+ * smallest power of two >= (2 + 2^-9) min h; particle i sits on the first
+ * level with L_l >= (2 + 2^-9) h_i; each level covers the bounding box of
+ * its own particles from origin floor(min/L_l) L_l; keys run level by
+ * level, then z, y, x (x fastest). */
+sg_status sg_build_neighbors(sg_ctx *ctx);
+
+/* SPH density of every gas particle (Eq. SPH-mass-density, self term
+ * included, h_ij = (h_i + h_j)/2) into st->rho.  Needs sg_build_neighbors. */
+sg_status sg_compute_density(sg_ctx *ctx);
+
+/* Accelerations at the current positions (Eq. dv_dt-SPH): with SG_SPH the
+ * pressure + artificial-viscosity sums and de/dt (Eq. de_dt-SPH) over the
+ * neighbour lists (needs density); with SG_GRAV the softened direct
+ * gravity over all N particles (and with SG_POT the potential).  Writes
+ * st->ax/ay/az = latest SPH part + latest gravity, and st->dedt.  After
+ * SG_PREDICT the SPH part uses the predicted velocities and energies. */
+sg_status sg_compute_accel(sg_ctx *ctx, uint32_t flags);
+
+/* Predictor-corrector update (Sec. 2.2, Eqs. v-predictor .. e-corrector).
+ * SG_PREDICT: vt = v + dt a, et = e + dt de/dt (kept in the workspace),
+ *   r += dt/2 (vt + v).  SG_CORRECT: v = (v + vt)/2 + dt/2 a,
+ *   e = (e + et)/2 + dt/2 de/dt, with a, de/dt evaluated after SG_PREDICT. */
+sg_status sg_kick_drift(sg_ctx *ctx, double dt, int32_t phase);
+
+/* One whole step, enqueue-only: [first call: neighbours, density,
+ * gravity] -> SPH(predictor) -> SG_PREDICT -> neighbours -> density ->
+ * gravity (once per step, reused by the next predictor) -> SPH(corrector)
+ * -> SG_CORRECT.  flags may add SG_POT. */
+sg_status sg_step(sg_ctx *ctx, double dt, uint32_t flags);
+
+/* Conserved quantities into d_out10 (device, 10 doubles): E_kin, E_int,
+ * E_pot (needs SG_POT computed), E_total, momentum (3), angular momentum
+ * (3); FP64 sums in a fixed order. */
+sg_status sg_diagnostics(sg_ctx *ctx, double *d_out10);
+
+/* What sg_export() copies (device -> device, after a stream sync). */
+typedef enum {
+    SG_X_KEYS = 0,      /* int32 [N_g] cell key of gas particle i           */
+    SG_X_COUNTS = 1,    /* int32 [M]   particles per cell                   */
+    SG_X_OFFSETS = 2,   /* int64 [M+1] exclusive prefix sums of COUNTS       */
+    SG_X_HMAX = 3,      /* double [M]  largest h in each cell (0 if empty)   */
+    SG_X_PERM = 4,      /* int32 [N_g] gas particle stored at sorted slot s  */
+    SG_X_NBR_OFF = 5,   /* int64 [N_g+1] CSR row offsets, rows by slot       */
+    SG_X_NBR_IDX = 6,   /* int32 [nnz] neighbour slots, ascending per row    */
+    SG_X_GRID = 7,      /* sg_grid_info, 1 element                           */
+    SG_X_GORDER = 8     /* int32 [N] gravity target order (SG_FP32C only)    */
+} sg_export_what;
+
+/* Host-readable grid description (SG_X_GRID). */
+typedef struct {
+    double L0;
+    int32_t nlev, pad;
+    double L[SG_MAX_LEVELS];
+    double org[SG_MAX_LEVELS][3];
+    int64_t dim[SG_MAX_LEVELS][3];
+    int64_t base[SG_MAX_LEVELS];
+    int64_t ncell[SG_MAX_LEVELS];
+    int64_t npart[SG_MAX_LEVELS];
+    double hmax[SG_MAX_LEVELS];
+    int64_t M;
+} sg_grid_info;
+
+/* Copy an internal array into caller memory: d_dst (device for arrays,
+ * host for SG_X_GRID) of cap_bytes bytes.  *n_out receives the element
+ * count.  SG_ECAPACITY if cap_bytes is too small (nothing copied). */
+sg_status sg_export(sg_ctx *ctx, int32_t what, void *d_dst, int64_t cap_bytes,
+                    int64_t *n_out);
+
+/* Wait for the stream, then report the device error word.  On
+ * SG_ECAPACITY, need[0] = cells required, need[1] = neighbour pairs
+ * required (need may be NULL). */
+sg_status sg_sync(sg_ctx *ctx, int64_t need[2]);
+
+/* Stage timing.  When enabled, every kernel group below is bracketed by a
+ * pair of HIP events on the context's stream; sg_profile_read() waits for
+ * the stream and returns, per stage, the summed milliseconds and the number
+ * of launches since the last enable.  Off by default; do not enable while
+ * capturing the stream into a graph. */
+typedef enum {
+    SG_ST_SORT = 0,       /* levels, keys, counts, offsets, reorder, gather */
+    SG_ST_NBR = 1,        /* neighbour count, offsets, fill                  */
+    SG_ST_DENSITY = 2,
+    SG_ST_SPH = 3,        /* EOS gather + pressure/viscosity sums            */
+    SG_ST_GRAV_PREP = 4,  /* FP32C: Morton order, sorted copies, boxes       */
+    SG_ST_GRAV = 5,       /* the pair kernel (+ split reduction)             */
+    SG_ST_UPDATE = 6,     /* predictor / corrector / combine                 */
+    SG_ST_DIAG = 7,
+    SG_NSTAGE = 8
+} sg_stage;
+sg_status sg_profile_enable(sg_ctx *ctx, int32_t on);
+sg_status sg_profile_read(sg_ctx *ctx, double ms[SG_NSTAGE], int64_t count[SG_NSTAGE]);
+
+/* Last error message of this context (static storage; never NULL). */
+const char *sg_last_error(const sg_ctx *ctx);
+
+/* Destroy the context (does not free the workspace or the state). */
+void sg_destroy(sg_ctx *ctx);
+
+/* Library version and the target architecture it was built for. */
+const char *sg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

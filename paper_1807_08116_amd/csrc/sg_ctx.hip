@@ -1,0 +1,694 @@
+// sg_ctx.hip -- host side of the C ABI: argument checks, the workspace
+// layout, and the order in which the force-evaluation kernels are enqueued
+// (the kernel sequence of the paper's predictor-corrector step, Sec. 3).
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Largest (split x N) product the automatic gravity launch can ask for.
+int64_t part_cap_elems(int64_t n) {
+    int64_t a = 64 * n, b = (int64_t(1) << 21) + n;
+    return a < b ? a : b;
+}
+
+struct layout {
+    size_t grid;
+    size_t key, perm, tmp;
+    size_t count, cursor, hmax, off;
+    size_t scan;
+    size_t xs, ys, zs, hs, ms, vxs, vys, vzs, es, rho_s, P_s, c_s;
+    size_t hs_f, ms_f, vx_f, vy_f, vz_f, rho_f, P_f, c_f;
+    size_t ncnt, nbr_off, nbr_idx;
+    size_t asx, asy, asz;
+    size_t gx, gy, gz, gpot;
+    size_t gorder, morton, gsorted;
+    size_t part;
+    size_t vtx, vty, vtz, et;
+    size_t diag;
+    size_t total;
+};
+
+layout make_layout(const sg_params* p, const sg_caps* c) {
+    layout L;
+    const int64_t ng = c->n_gas_cap, n = c->n_gas_cap + c->n_halo_cap;
+    const int64_t C = c->cell_cap, Z = c->nnz_cap;
+    const bool f32 = p->precision == SG_FP32C;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += al(bytes ? bytes : 1);
+        return at;
+    };
+    L.grid = take(sizeof(sg_grid_dev));
+    L.key = take(4 * ng);
+    L.perm = take(4 * ng);
+    L.tmp = take(4 * ng);
+    L.count = take(4 * C);
+    L.cursor = take(4 * C);
+    L.hmax = take(8 * C);
+    L.off = take(8 * (C + 1));
+    L.scan = take(sg_scan_tmp_bytes(C > ng + 1 ? C : ng + 1));
+    size_t* f64s[] = {&L.xs, &L.ys, &L.zs, &L.hs, &L.ms, &L.vxs, &L.vys,
+                      &L.vzs, &L.es, &L.rho_s, &L.P_s, &L.c_s};
+    for (size_t* q : f64s) *q = take(8 * ng);
+    size_t* f32s[] = {&L.hs_f, &L.ms_f, &L.vx_f, &L.vy_f, &L.vz_f, &L.rho_f, &L.P_f, &L.c_f};
+    for (size_t* q : f32s) *q = take(f32 ? 4 * ng : 0);
+    L.ncnt = take(4 * ng);
+    L.nbr_off = take(8 * (ng + 1));
+    L.nbr_idx = take(4 * Z);
+    L.asx = take(8 * ng);
+    L.asy = take(8 * ng);
+    L.asz = take(8 * ng);
+    L.gx = take(8 * n);
+    L.gy = take(8 * n);
+    L.gz = take(8 * n);
+    L.gpot = take(8 * n);
+    L.gorder = take(f32 ? 4 * n : 0);
+    L.morton = take(f32 ? sg_morton_tmp_bytes(n) : 0);
+    L.gsorted = take(f32 ? sg_grav_sorted_bytes(n) : 0);
+    L.part = take(8 * 4 * (size_t)part_cap_elems(n));
+    L.vtx = take(8 * n);
+    L.vty = take(8 * n);
+    L.vtz = take(8 * n);
+    L.et = take(8 * ng);
+    L.diag = take(sg_diag_tmp_bytes());
+    L.total = o;
+    return L;
+}
+
+bool params_ok(const sg_params* p, const char** why) {
+    if (!p) return *why = "params is NULL", false;
+    if (!(p->eps > 0.0) || !__builtin_isfinite(p->eps)) return *why = "eps must be > 0", false;
+    if (!__builtin_isfinite(p->G)) return *why = "G must be finite", false;
+    if (!(p->gamma > 1.0) || !__builtin_isfinite(p->gamma)) return *why = "gamma must be > 1", false;
+    if (!(p->alpha >= 0.0) || !(p->beta >= 0.0) || !__builtin_isfinite(p->alpha) ||
+        !__builtin_isfinite(p->beta))
+        return *why = "alpha, beta must be >= 0", false;
+    if (!(p->eta > 0.0) || !__builtin_isfinite(p->eta)) return *why = "eta must be > 0", false;
+    if (p->precision != SG_FP64 && p->precision != SG_FP32C)
+        return *why = "precision must be SG_FP64 or SG_FP32C", false;
+    if (p->grav_ipl != 0 && p->grav_ipl != 1 && p->grav_ipl != 2 && p->grav_ipl != 4)
+        return *why = "grav_ipl must be 0, 1, 2 or 4", false;
+    if (p->grav_split < 0 || p->grav_split > 64) return *why = "grav_split must be in [0, 64]", false;
+    for (int r : p->reserved)
+        if (r != 0) return *why = "reserved fields must be zero", false;
+    return true;
+}
+
+bool caps_ok(const sg_caps* c, const char** why) {
+    if (!c) return *why = "caps is NULL", false;
+    if (c->n_gas_cap < 0 || c->n_halo_cap < 0 || c->cell_cap < 0 || c->nnz_cap < 0)
+        return *why = "capacities must be >= 0", false;
+    if (c->n_gas_cap + c->n_halo_cap < 1) return *why = "need room for at least one particle", false;
+    if (c->n_gas_cap + c->n_halo_cap > 2147483647ll || c->cell_cap > 2147483646ll)
+        return *why = "particle and cell capacities must fit in int32", false;
+    if (c->n_gas_cap > 0 && (c->cell_cap < 1 || c->nnz_cap < 1))
+        return *why = "gas needs cell_cap >= 1 and nnz_cap >= 1", false;
+    return true;
+}
+
+}  // namespace
+
+struct sg_ctx {
+    sg_params prm;
+    sg_caps caps;
+    layout L;
+    char* ws;
+    hipStream_t st;
+    // bound state
+    bool bound;
+    int64_t ng, nh, n;
+    sg_state s;
+    // validity of cached results for the current positions / velocities
+    bool have_nbr, have_rho, have_grav, have_pot, have_sph;
+    bool predicted;        // between SG_PREDICT and SG_CORRECT
+    bool accel_after_predict;
+    char msg[256];
+    // stage timing
+    bool prof;
+    struct mark {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<mark> marks;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[SG_NSTAGE];
+    int64_t prof_n[SG_NSTAGE];
+    int open_stage;
+    hipEvent_t open_ev;
+
+    hipEvent_t take_event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void begin(int stage) {
+        if (!prof) return;
+        open_stage = stage;
+        open_ev = take_event();
+        if (open_ev) (void)hipEventRecord(open_ev, st);
+    }
+    void end() {
+        if (!prof || !open_ev) return;
+        hipEvent_t e = take_event();
+        if (e) {
+            (void)hipEventRecord(e, st);
+            marks.push_back(mark{open_stage, open_ev, e});
+        }
+        open_ev = nullptr;
+    }
+
+    template <typename T>
+    T* at(size_t off) const {
+        return (T*)(ws + off);
+    }
+    sg_grid_dev* grid() const { return at<sg_grid_dev>(L.grid); }
+    sg_status fail(sg_status code, const char* m) {
+        snprintf(msg, sizeof(msg), "%s", m);
+        return code;
+    }
+    sg_status check_launch(const char* what) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            snprintf(msg, sizeof(msg), "%s: %s", what, hipGetErrorString(e));
+            return SG_EDEVICE;
+        }
+        return SG_OK;
+    }
+    sg_sph_bufs sph() const {
+        sg_sph_bufs b;
+        b.xs = at<double>(L.xs);
+        b.ys = at<double>(L.ys);
+        b.zs = at<double>(L.zs);
+        b.hs = at<double>(L.hs);
+        b.ms = at<double>(L.ms);
+        b.vxs = at<double>(L.vxs);
+        b.vys = at<double>(L.vys);
+        b.vzs = at<double>(L.vzs);
+        b.es = at<double>(L.es);
+        b.rho_s = at<double>(L.rho_s);
+        b.P_s = at<double>(L.P_s);
+        b.c_s = at<double>(L.c_s);
+        b.hs_f = at<float>(L.hs_f);
+        b.ms_f = at<float>(L.ms_f);
+        b.vx_f = at<float>(L.vx_f);
+        b.vy_f = at<float>(L.vy_f);
+        b.vz_f = at<float>(L.vz_f);
+        b.rho_f = at<float>(L.rho_f);
+        b.P_f = at<float>(L.P_f);
+        b.c_f = at<float>(L.c_f);
+        b.perm = at<int32_t>(L.perm);
+        b.nbr_off = at<int64_t>(L.nbr_off);
+        b.nbr_idx = at<int32_t>(L.nbr_idx);
+        return b;
+    }
+    void invalidate_positions() {
+        have_nbr = have_rho = have_grav = have_pot = have_sph = false;
+    }
+};
+
+namespace {
+
+sg_status need_bound(sg_ctx* c) {
+    if (!c) return SG_EINVAL;
+    if (!c->bound) return c->fail(SG_ESTATE, "no state bound (call sg_bind_state)");
+    return SG_OK;
+}
+
+// Automatic gravity launch shape: enough workgroups to cover the 256 CUs
+// several times over, targets per lane as large as that allows.
+void grav_shape(const sg_ctx* c, int* ipl, int* split) {
+    const int64_t n = c->n;
+    int p = c->prm.grav_ipl;
+    if (p == 0) p = n >= 4 * 256 * 2048 ? 4 : (n >= 2 * 256 * 1024 ? 2 : 1);
+    int s = c->prm.grav_split;
+    const int64_t iblocks = (n + 256 * p - 1) / (256 * p);
+    if (s == 0) {
+        int64_t want = (2048 + iblocks - 1) / iblocks;
+        s = (int)(want < 1 ? 1 : (want > 64 ? 64 : want));
+    }
+    // the partial buffer bounds split x n
+    while (s > 1 && (int64_t)s * n > part_cap_elems(c->caps.n_gas_cap + c->caps.n_halo_cap)) --s;
+    *ipl = p;
+    *split = s;
+}
+
+sg_status do_build(sg_ctx* c) {
+    const int64_t ng = c->ng;
+    if (ng == 0) {
+        c->have_nbr = true;
+        return SG_OK;
+    }
+    hipStream_t st = c->st;
+    sg_grid_dev* g = c->grid();
+    const sg_state& s = c->s;
+    const int64_t C = c->caps.cell_cap;
+    int32_t* key = c->at<int32_t>(c->L.key);
+    int32_t* count = c->at<int32_t>(c->L.count);
+    int32_t* cursor = c->at<int32_t>(c->L.cursor);
+    unsigned long long* hmax = c->at<unsigned long long>(c->L.hmax);
+    int64_t* off = c->at<int64_t>(c->L.off);
+    void* scan = c->at<void>(c->L.scan);
+    sg_sph_bufs b = c->sph();
+    c->begin(SG_ST_SORT);
+    sg_launch_grid_reset(g, st);
+    sg_launch_grid_reduce(s.x, s.y, s.z, s.h, ng, g, st);
+    sg_launch_grid_finish(g, C, st);
+    sg_launch_cells_clear(g, count, hmax, cursor, C, st);
+    sg_launch_keys_count(s.x, s.y, s.z, s.h, ng, g, key, count, hmax, st);
+    sg_launch_scan(count, off, 0, &g->M, C, scan, st);
+    sg_launch_scatter_rank(key, ng, g, off, cursor, c->at<int32_t>(c->L.tmp),
+                           c->at<int32_t>(c->L.perm), st);
+    sg_launch_gather_gas(b.perm, ng, g, s.x, s.y, s.z, s.h, s.m, b.xs, b.ys, b.zs, b.hs, b.ms, st);
+    c->end();
+    c->begin(SG_ST_NBR);
+    int32_t* ncnt = c->at<int32_t>(c->L.ncnt);
+    int64_t* nbr_off = c->at<int64_t>(c->L.nbr_off);
+    sg_launch_nbr_count(g, ng, b.xs, b.ys, b.zs, b.hs, off, ncnt, st);
+    sg_launch_scan(ncnt, nbr_off, ng, nullptr, ng, scan, st);
+    sg_launch_nbr_check(g, nbr_off, ng, c->caps.nnz_cap, st);
+    sg_launch_nbr_fill(g, ng, b.xs, b.ys, b.zs, b.hs, off, nbr_off, c->at<int32_t>(c->L.nbr_idx),
+                       c->caps.nnz_cap, st);
+    c->end();
+    sg_status r = c->check_launch("neighbour build");
+    if (r != SG_OK) return r;
+    c->have_nbr = true;
+    c->have_rho = false;
+    return SG_OK;
+}
+
+sg_status do_density(sg_ctx* c) {
+    if (c->ng > 0) {
+        if (!c->have_nbr) return c->fail(SG_ESTATE, "density needs neighbour lists");
+        c->begin(SG_ST_DENSITY);
+        sg_launch_density(c->sph(), c->grid(), c->ng, c->prm.precision, c->s.rho, c->st);
+        c->end();
+        sg_status r = c->check_launch("density");
+        if (r != SG_OK) return r;
+    }
+    c->have_rho = true;
+    return SG_OK;
+}
+
+sg_status do_gravity(sg_ctx* c, bool pot) {
+    sg_grav_args a;
+    a.x = c->s.x;
+    a.y = c->s.y;
+    a.z = c->s.z;
+    a.m = c->s.m;
+    a.n = c->n;
+    a.G = c->prm.G;
+    a.eps = c->prm.eps;
+    a.precision = c->prm.precision;
+    grav_shape(c, &a.ipl, &a.split);
+    a.with_pot = pot ? 1 : 0;
+    a.order = nullptr;
+    a.sorted = c->at<void>(c->L.gsorted);
+    a.gx = c->at<double>(c->L.gx);
+    a.gy = c->at<double>(c->L.gy);
+    a.gz = c->at<double>(c->L.gz);
+    a.gpot = c->s.pot ? c->s.pot : c->at<double>(c->L.gpot);
+    a.part = c->at<double>(c->L.part);
+    if (c->prm.precision == SG_FP32C) {
+        int32_t* order = c->at<int32_t>(c->L.gorder);
+        a.order = order;
+        c->begin(SG_ST_GRAV_PREP);
+        sg_launch_morton_order(c->s.x, c->s.y, c->s.z, c->n, c->grid(), order,
+                               c->at<void>(c->L.morton), c->st);
+        const int rc = sg_launch_grav_sorted(a, c->st);
+        c->end();
+        if (rc != 0) return c->fail(SG_EINVAL, "gravity preparation: missing buffer");
+    }
+    c->begin(SG_ST_GRAV);
+    const int rc = sg_launch_gravity(a, c->st);
+    c->end();
+    if (rc != 0) return c->fail(SG_EINVAL, "gravity: missing buffer");
+    sg_status r = c->check_launch("gravity");
+    if (r != SG_OK) return r;
+    c->have_grav = true;
+    c->have_pot = pot;
+    return SG_OK;
+}
+
+sg_status do_sph(sg_ctx* c) {
+    if (c->ng == 0) {
+        c->have_sph = true;
+        return SG_OK;
+    }
+    if (!c->have_rho) return c->fail(SG_ESTATE, "SPH forces need the density");
+    const double* vx = c->predicted ? c->at<double>(c->L.vtx) : c->s.vx;
+    const double* vy = c->predicted ? c->at<double>(c->L.vty) : c->s.vy;
+    const double* vz = c->predicted ? c->at<double>(c->L.vtz) : c->s.vz;
+    const double* e = c->predicted ? c->at<double>(c->L.et) : c->s.e;
+    sg_sph_bufs b = c->sph();
+    c->begin(SG_ST_SPH);
+    sg_launch_sph_prep(b, c->grid(), c->ng, c->prm.precision, c->prm.gamma, vx, vy, vz, e, c->st);
+    sg_launch_sph_force(b, c->grid(), c->ng, c->prm.precision, c->prm.alpha, c->prm.beta,
+                        c->prm.eta, c->at<double>(c->L.asx), c->at<double>(c->L.asy),
+                        c->at<double>(c->L.asz), c->s.dedt, c->st);
+    c->end();
+    sg_status r = c->check_launch("SPH forces");
+    if (r != SG_OK) return r;
+    c->have_sph = true;
+    return SG_OK;
+}
+
+void do_combine(sg_ctx* c) {
+    const bool sph = c->have_sph && c->ng > 0;
+    c->begin(SG_ST_UPDATE);
+    sg_launch_combine(c->n, c->ng, sph ? c->at<double>(c->L.asx) : nullptr,
+                      sph ? c->at<double>(c->L.asy) : nullptr,
+                      sph ? c->at<double>(c->L.asz) : nullptr,
+                      c->have_grav ? c->at<double>(c->L.gx) : nullptr,
+                      c->have_grav ? c->at<double>(c->L.gy) : nullptr,
+                      c->have_grav ? c->at<double>(c->L.gz) : nullptr, c->s.ax, c->s.ay, c->s.az,
+                      c->st);
+    c->end();
+}
+
+sg_status do_accel(sg_ctx* c, uint32_t flags) {
+    if (flags & ~(SG_SPH | SG_GRAV | SG_POT)) return c->fail(SG_EINVAL, "unknown flags");
+    if ((flags & SG_POT) && !(flags & SG_GRAV)) return c->fail(SG_EINVAL, "SG_POT needs SG_GRAV");
+    sg_status r;
+    if (flags & SG_GRAV) {
+        if ((r = do_gravity(c, (flags & SG_POT) != 0)) != SG_OK) return r;
+    }
+    if (flags & SG_SPH) {
+        if ((r = do_sph(c)) != SG_OK) return r;
+    }
+    do_combine(c);
+    if (c->predicted) c->accel_after_predict = true;
+    return c->check_launch("combine");
+}
+
+sg_status do_kick_drift(sg_ctx* c, double dt, int phase) {
+    if (!__builtin_isfinite(dt)) return c->fail(SG_EINVAL, "dt must be finite");
+    const sg_state& s = c->s;
+    double* vtx = c->at<double>(c->L.vtx);
+    double* vty = c->at<double>(c->L.vty);
+    double* vtz = c->at<double>(c->L.vtz);
+    double* et = c->at<double>(c->L.et);
+    if (phase == SG_PREDICT) {
+        if (c->predicted) return c->fail(SG_ESTATE, "SG_PREDICT twice without SG_CORRECT");
+        if (!c->have_grav || !(c->have_sph || c->ng == 0))
+            return c->fail(SG_ESTATE, "SG_PREDICT needs gravity and SPH forces at the current state");
+        c->begin(SG_ST_UPDATE);
+        sg_launch_predict(c->n, c->ng, dt, s.x, s.y, s.z, s.vx, s.vy, s.vz, s.e, s.ax, s.ay, s.az,
+                          s.dedt, vtx, vty, vtz, et, c->st);
+        c->end();
+        c->invalidate_positions();
+        c->predicted = true;
+        c->accel_after_predict = false;
+    } else if (phase == SG_CORRECT) {
+        if (!c->predicted) return c->fail(SG_ESTATE, "SG_CORRECT without SG_PREDICT");
+        if (!c->accel_after_predict || !c->have_grav || !(c->have_sph || c->ng == 0))
+            return c->fail(SG_ESTATE, "SG_CORRECT needs gravity and SPH forces after SG_PREDICT");
+        c->begin(SG_ST_UPDATE);
+        sg_launch_correct(c->n, c->ng, dt, s.vx, s.vy, s.vz, s.e, vtx, vty, vtz, et, s.ax, s.ay,
+                          s.az, s.dedt, c->st);
+        c->end();
+        c->predicted = false;
+        c->have_sph = false;       // the SPH part was evaluated with the predicted velocities
+    } else {
+        return c->fail(SG_EINVAL, "phase must be SG_PREDICT or SG_CORRECT");
+    }
+    return c->check_launch("kick/drift");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sg_workspace_bytes(const sg_params* prm, const sg_caps* caps) {
+    const char* why;
+    if (!params_ok(prm, &why) || !caps_ok(caps, &why)) return 0;
+    return make_layout(prm, caps).total;
+}
+
+sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace,
+                    size_t ws_bytes, void* stream, sg_ctx** out) {
+    if (!out) return SG_EINVAL;
+    *out = nullptr;
+    const char* why = nullptr;
+    if (!params_ok(prm, &why) || !caps_ok(caps, &why)) return SG_EINVAL;
+    if (!d_workspace || ((uintptr_t)d_workspace & (kAlign - 1))) return SG_EINVAL;
+    layout L = make_layout(prm, caps);
+    if (ws_bytes < L.total) return SG_EINVAL;
+    sg_ctx* c = new (std::nothrow) sg_ctx();
+    if (!c) return SG_EINVAL;
+    c->prm = *prm;
+    c->caps = *caps;
+    c->L = L;
+    c->ws = (char*)d_workspace;
+    c->st = (hipStream_t)stream;
+    c->bound = false;
+    c->ng = c->nh = c->n = 0;
+    memset(&c->s, 0, sizeof(c->s));
+    c->invalidate_positions();
+    c->predicted = false;
+    c->accel_after_predict = false;
+    c->msg[0] = 0;
+    c->prof = false;
+    c->open_ev = nullptr;
+    c->open_stage = 0;
+    for (int k = 0; k < SG_NSTAGE; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    sg_launch_status_clear(c->grid(), c->st);
+    sg_launch_grid_reset(c->grid(), c->st);
+    if (c->check_launch("create") != SG_OK) {
+        delete c;
+        return SG_EDEVICE;
+    }
+    *out = c;
+    return SG_OK;
+}
+
+sg_status sg_bind_state(sg_ctx* c, int64_t n_gas, int64_t n_halo, const sg_state* st) {
+    if (!c) return SG_EINVAL;
+    if (!st) return c->fail(SG_EINVAL, "state is NULL");
+    if (n_gas < 0 || n_halo < 0 || n_gas + n_halo < 1)
+        return c->fail(SG_EINVAL, "need n_gas, n_halo >= 0 and at least one particle");
+    if (n_gas > c->caps.n_gas_cap || n_halo > c->caps.n_halo_cap)
+        return c->fail(SG_EINVAL, "particle counts exceed the capacities");
+    if (!st->x || !st->y || !st->z || !st->vx || !st->vy || !st->vz || !st->m || !st->ax ||
+        !st->ay || !st->az)
+        return c->fail(SG_EINVAL, "a required state pointer is NULL");
+    if (n_gas > 0 && (!st->h || !st->e || !st->dedt || !st->rho))
+        return c->fail(SG_EINVAL, "gas needs h, e, dedt and rho");
+    const void* ptrs[] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, st->m, st->ax, st->ay,
+                          st->az, st->h, st->e, st->dedt, st->rho, st->pot};
+    for (const void* p : ptrs)
+        if (p && ((uintptr_t)p & 7)) return c->fail(SG_EINVAL, "state pointers must be 8-byte aligned");
+    c->s = *st;
+    c->ng = n_gas;
+    c->nh = n_halo;
+    c->n = n_gas + n_halo;
+    c->bound = true;
+    c->invalidate_positions();
+    c->predicted = false;
+    c->accel_after_predict = false;
+    sg_launch_status_clear(c->grid(), c->st);
+    return c->check_launch("bind");
+}
+
+sg_status sg_build_neighbors(sg_ctx* c) {
+    sg_status r = need_bound(c);
+    return r != SG_OK ? r : do_build(c);
+}
+
+sg_status sg_compute_density(sg_ctx* c) {
+    sg_status r = need_bound(c);
+    return r != SG_OK ? r : do_density(c);
+}
+
+sg_status sg_compute_accel(sg_ctx* c, uint32_t flags) {
+    sg_status r = need_bound(c);
+    if (r != SG_OK) return r;
+    return do_accel(c, flags);
+}
+
+sg_status sg_kick_drift(sg_ctx* c, double dt, int32_t phase) {
+    sg_status r = need_bound(c);
+    return r != SG_OK ? r : do_kick_drift(c, dt, phase);
+}
+
+sg_status sg_step(sg_ctx* c, double dt, uint32_t flags) {
+    sg_status r = need_bound(c);
+    if (r != SG_OK) return r;
+    if (flags & ~SG_POT) return c->fail(SG_EINVAL, "sg_step accepts only SG_POT");
+    if (!__builtin_isfinite(dt)) return c->fail(SG_EINVAL, "dt must be finite");
+    if (c->predicted) return c->fail(SG_ESTATE, "sg_step inside a predict/correct pair");
+    const uint32_t gflags = SG_GRAV | (flags & SG_POT);
+    // forces at r(t): neighbours and density are reused from the previous
+    // step's corrector (positions unchanged since), gravity likewise.
+    if (!c->have_nbr && (r = do_build(c)) != SG_OK) return r;
+    if (!c->have_rho && (r = do_density(c)) != SG_OK) return r;
+    if (!c->have_grav || ((flags & SG_POT) && !c->have_pot))
+        if ((r = do_gravity(c, (flags & SG_POT) != 0)) != SG_OK) return r;
+    if ((r = do_sph(c)) != SG_OK) return r;                 // predictor right-hand side
+    do_combine(c);
+    if ((r = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return r;
+    if ((r = do_build(c)) != SG_OK) return r;
+    if ((r = do_density(c)) != SG_OK) return r;
+    if ((r = do_accel(c, gflags | SG_SPH)) != SG_OK) return r;   // corrector right-hand side
+    return do_kick_drift(c, dt, SG_CORRECT);
+}
+
+sg_status sg_diagnostics(sg_ctx* c, double* d_out10) {
+    sg_status r = need_bound(c);
+    if (r != SG_OK) return r;
+    if (!d_out10) return c->fail(SG_EINVAL, "output is NULL");
+    const double* pot = nullptr;
+    if (c->have_pot) pot = c->s.pot ? c->s.pot : c->at<double>(c->L.gpot);
+    c->begin(SG_ST_DIAG);
+    sg_launch_diagnostics(c->n, c->ng, c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.m,
+                          c->s.e, pot, c->at<double>(c->L.diag), d_out10, c->st);
+    c->end();
+    return c->check_launch("diagnostics");
+}
+
+sg_status sg_export(sg_ctx* c, int32_t what, void* dst, int64_t cap_bytes, int64_t* n_out) {
+    sg_status r = need_bound(c);
+    if (r != SG_OK) return r;
+    if (!dst || !n_out) return c->fail(SG_EINVAL, "destination or n_out is NULL");
+    if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(SG_EDEVICE, "stream sync failed");
+    sg_grid_dev g;
+    if (hipMemcpy(&g, c->grid(), sizeof(g), hipMemcpyDeviceToHost) != hipSuccess)
+        return c->fail(SG_EDEVICE, "reading the grid failed");
+    const int64_t ng = c->ng, M = g.M;
+    const void* src = nullptr;
+    int64_t n = 0, esz = 0;
+    switch (what) {
+        case SG_X_KEYS: src = c->at<void>(c->L.key); n = ng; esz = 4; break;
+        case SG_X_COUNTS: src = c->at<void>(c->L.count); n = M; esz = 4; break;
+        case SG_X_OFFSETS: src = c->at<void>(c->L.off); n = M + 1; esz = 8; break;
+        case SG_X_HMAX: src = c->at<void>(c->L.hmax); n = M; esz = 8; break;
+        case SG_X_PERM: src = c->at<void>(c->L.perm); n = ng; esz = 4; break;
+        case SG_X_NBR_OFF: src = c->at<void>(c->L.nbr_off); n = ng + 1; esz = 8; break;
+        case SG_X_NBR_IDX: src = c->at<void>(c->L.nbr_idx); n = g.nnz; esz = 4; break;
+        case SG_X_GORDER:
+            if (c->prm.precision != SG_FP32C) return c->fail(SG_EINVAL, "no gravity order in FP64 form");
+            src = c->at<void>(c->L.gorder); n = c->n; esz = 4; break;
+        case SG_X_GRID: {
+            if (cap_bytes < (int64_t)sizeof(sg_grid_info)) return c->fail(SG_ECAPACITY, "buffer too small");
+            sg_grid_info info;
+            memset(&info, 0, sizeof(info));
+            info.L0 = g.L0;
+            info.nlev = g.nlev;
+            for (int l = 0; l < SG_MAXLEV; ++l) {
+                info.L[l] = g.L[l];
+                info.base[l] = g.base[l];
+                info.ncell[l] = g.ncell[l];
+                info.npart[l] = (int64_t)g.npart[l];
+                info.hmax[l] = g.hmaxlev[l];
+                for (int d = 0; d < 3; ++d) {
+                    info.org[l][d] = g.org[l][d];
+                    info.dim[l][d] = g.dim[l][d];
+                }
+            }
+            info.M = g.M;
+            memcpy(dst, &info, sizeof(info));
+            *n_out = 1;
+            return SG_OK;
+        }
+        default: return c->fail(SG_EINVAL, "unknown export");
+    }
+    *n_out = n;
+    if (n * esz > cap_bytes) return c->fail(SG_ECAPACITY, "destination too small");
+    if (n > 0 && hipMemcpy(dst, src, (size_t)(n * esz), hipMemcpyDeviceToDevice) != hipSuccess)
+        return c->fail(SG_EDEVICE, "export copy failed");
+    return SG_OK;
+}
+
+sg_status sg_sync(sg_ctx* c, int64_t need[2]) {
+    if (!c) return SG_EINVAL;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(SG_EDEVICE, "stream sync failed");
+    sg_grid_dev g;
+    if (hipMemcpy(&g, c->grid(), sizeof(g), hipMemcpyDeviceToHost) != hipSuccess)
+        return c->fail(SG_EDEVICE, "reading the status failed");
+    if (need) {
+        need[0] = g.need_cells;
+        need[1] = g.need_nnz;
+    }
+    if (g.err == 0) return SG_OK;
+    sg_launch_status_clear(c->grid(), c->st);
+    (void)hipStreamSynchronize(c->st);
+    c->invalidate_positions();
+    if (g.err & SGE_NONFINITE)
+        return c->fail(SG_ENONFINITE, "non-finite position or smoothing length <= 0");
+    if (g.err & SGE_LEVELS)
+        return c->fail(SG_ERANGE, "smoothing lengths span more than SG_MAX_LEVELS levels");
+    if (g.err & SGE_GRID) return c->fail(SG_ERANGE, "grid level too large for int32 cell keys");
+    snprintf(c->msg, sizeof(c->msg), "capacity exceeded: need %lld cells, %lld neighbour pairs",
+             (long long)g.need_cells, (long long)g.need_nnz);
+    return SG_ECAPACITY;
+}
+
+const char* sg_last_error(const sg_ctx* c) { return c ? c->msg : "null context"; }
+
+sg_status sg_profile_enable(sg_ctx* c, int32_t on) {
+    if (!c) return SG_EINVAL;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(SG_EDEVICE, "stream sync failed");
+    for (auto& mk : c->marks) {
+        c->pool.push_back(mk.a);
+        c->pool.push_back(mk.b);
+    }
+    c->marks.clear();
+    for (int k = 0; k < SG_NSTAGE; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    c->prof = on != 0;
+    return SG_OK;
+}
+
+sg_status sg_profile_read(sg_ctx* c, double ms[SG_NSTAGE], int64_t count[SG_NSTAGE]) {
+    if (!c || !ms || !count) return SG_EINVAL;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(SG_EDEVICE, "stream sync failed");
+    for (auto& mk : c->marks) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, mk.a, mk.b) == hipSuccess) {
+            c->prof_ms[mk.stage] += t;
+            c->prof_n[mk.stage] += 1;
+        }
+        c->pool.push_back(mk.a);
+        c->pool.push_back(mk.b);
+    }
+    c->marks.clear();
+    for (int k = 0; k < SG_NSTAGE; ++k) {
+        ms[k] = c->prof_ms[k];
+        count[k] = c->prof_n[k];
+    }
+    return SG_OK;
+}
+
+void sg_destroy(sg_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    for (auto& mk : c->marks) {
+        (void)hipEventDestroy(mk.a);
+        (void)hipEventDestroy(mk.b);
+    }
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* sg_version(void) { return "sphgrav 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+// sg_internal.h -- device-side structures and launcher declarations shared by
+// the translation units of libsphgrav.so (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sphgrav.h"
+
+#define SG_MAXLEV SG_MAX_LEVELS
+
+// Device error bits (latched; cleared by sg_create / sg_bind_state).
+enum : uint32_t {
+    SGE_LEVELS = 1u,      // smoothing lengths need more than SG_MAXLEV levels
+    SGE_CELLS = 2u,       // M > cell_cap
+    SGE_NNZ = 4u,         // neighbour pairs > nnz_cap
+    SGE_NONFINITE = 8u,   // non-finite position, h <= 0 or non-finite h
+    SGE_GRID = 16u,       // a level's cell count does not fit in int32
+};
+#define SGE_SORT_FATAL (SGE_LEVELS | SGE_CELLS | SGE_NONFINITE | SGE_GRID)
+
+// Grid of smoothing-length levels plus the device status word.  Lives in
+// the workspace; written only by device code during a neighbour build.
+struct sg_grid_dev {
+    // reduction inputs (order-preserving u64 images of doubles)
+    unsigned long long hmin_bits;
+    unsigned long long lo[SG_MAXLEV][3];
+    unsigned long long hi[SG_MAXLEV][3];
+    unsigned long long hmax_bits[SG_MAXLEV];
+    unsigned long long npart[SG_MAXLEV];
+    // finished grid
+    double L0;
+    double L[SG_MAXLEV], invL[SG_MAXLEV];
+    double org[SG_MAXLEV][3];
+    int64_t dim[SG_MAXLEV][3];
+    int64_t base[SG_MAXLEV];
+    int64_t ncell[SG_MAXLEV];
+    double hmaxlev[SG_MAXLEV];
+    int32_t nlev, pad0;
+    int64_t M;
+    // gravity-order bounding box over all N (order-preserving u64 images)
+    unsigned long long glo[3], ghi[3];
+    // status
+    uint32_t err, pad1;
+    int64_t need_cells, need_nnz;
+    int64_t nnz;
+};
+
+// Order-preserving map of doubles onto u64 (for integer atomic min/max).
+__host__ __device__ inline unsigned long long sg_ord(double v) {
+    unsigned long long b = (unsigned long long)__builtin_bit_cast(long long, v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double sg_unord(unsigned long long m) {
+    unsigned long long b = (m >> 63) ? (m & 0x7fffffffffffffffull) : ~m;
+    return __builtin_bit_cast(double, (long long)b);
+}
+
+// ---- launchers (each defined in the translation unit of its kernels) ----
+// Scans: exclusive prefix sums of int32 counts into int64 offsets, with
+// out[n] = total.  n is read from *n_dev when n_dev != nullptr (device-side
+// sizes), else n_host; cap bounds the launch.
+size_t sg_scan_tmp_bytes(int64_t cap);
+void sg_launch_scan(const int32_t* in, int64_t* out, int64_t n_host, const int64_t* n_dev,
+                    int64_t cap, void* tmp, hipStream_t st);
+
+// Gas sort chain.
+void sg_launch_grid_reset(sg_grid_dev* g, hipStream_t st);   // keeps the error word
+void sg_launch_status_clear(sg_grid_dev* g, hipStream_t st);
+void sg_launch_grid_reduce(const double* x, const double* y, const double* z, const double* h,
+                           int64_t ng, sg_grid_dev* g, hipStream_t st);
+void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, hipStream_t st);
+void sg_launch_cells_clear(sg_grid_dev* g, int32_t* count, unsigned long long* hmax,
+                           int32_t* cursor, int64_t cell_cap, hipStream_t st);
+void sg_launch_keys_count(const double* x, const double* y, const double* z, const double* h,
+                          int64_t ng, sg_grid_dev* g, int32_t* key, int32_t* count,
+                          unsigned long long* hmax, hipStream_t st);
+void sg_launch_scatter_rank(const int32_t* key, int64_t ng, const sg_grid_dev* g,
+                            const int64_t* off, int32_t* cursor, int32_t* tmp, int32_t* perm,
+                            hipStream_t st);
+void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
+                          const double* x, const double* y, const double* z, const double* h,
+                          const double* m, double* xs, double* ys, double* zs, double* hs,
+                          double* ms, hipStream_t st);
+
+// Neighbour lists.
+void sg_launch_nbr_count(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
+                         const double* zs, const double* hs, const int64_t* off, int32_t* cnt,
+                         hipStream_t st);
+void sg_launch_nbr_check(sg_grid_dev* g, const int64_t* nbr_off, int64_t ng, int64_t nnz_cap,
+                         hipStream_t st);
+void sg_launch_nbr_fill(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
+                        const double* zs, const double* hs, const int64_t* off,
+                        const int64_t* nbr_off, int32_t* nbr_idx, int64_t nnz_cap,
+                        hipStream_t st);
+
+// SPH.
+struct sg_sph_bufs {
+    // sorted gas state (FP64)
+    double *xs, *ys, *zs, *hs, *ms;
+    double *vxs, *vys, *vzs, *es;
+    double *rho_s, *P_s, *c_s;          // rho, p/rho^2, sound speed
+    // FP32 mirrors used by the FP32C form
+    float *hs_f, *ms_f, *vx_f, *vy_f, *vz_f, *rho_f, *P_f, *c_f;
+    const int32_t* perm;
+    const int64_t* nbr_off;
+    const int32_t* nbr_idx;
+};
+void sg_launch_density(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
+                       double* rho_out, hipStream_t st);
+void sg_launch_sph_prep(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
+                        double gamma, const double* vx, const double* vy, const double* vz,
+                        const double* e, hipStream_t st);
+// SPH acceleration (asx/asy/asz) and de/dt, both in particle order.
+void sg_launch_sph_force(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
+                         double alpha, double beta, double eta, double* asx, double* asy,
+                         double* asz, double* dedt, hipStream_t st);
+
+// Gravity.
+struct sg_grav_args {
+    const double *x, *y, *z, *m;
+    int64_t n;
+    double G, eps;
+    int precision, ipl, split, with_pot;
+    const int32_t* order;               // FP32C: Morton order of the particles, else null
+    void* sorted;                       // FP32C: scratch of sg_grav_sorted_bytes(n)
+    const double *xs, *ys, *zs, *ms;    // (set by the launcher) sorted copies
+    const void* sbox;                   // (set by the launcher) sub-tile boxes
+    double *gx, *gy, *gz, *gpot;        // outputs [n], particle order
+    double* part;                       // split partials [4][split][n] when split > 1
+};
+size_t sg_grav_sorted_bytes(int64_t n);
+// FP32C: Morton-ordered copies of x, y, z, m and the boxes of their
+// 64-particle runs (needs a.order and a.sorted).
+// Both return -1 (and launch nothing) when a required pointer is missing.
+int sg_launch_grav_sorted(const sg_grav_args& a, hipStream_t st);
+int sg_launch_gravity(const sg_grav_args& a, hipStream_t st);
+
+// Spatial (Morton) order of all N particles for the FP32C gravity targets.
+size_t sg_morton_tmp_bytes(int64_t n);
+void sg_launch_morton_order(const double* x, const double* y, const double* z, int64_t n,
+                            sg_grid_dev* g, int32_t* order, void* tmp, hipStream_t st);
+
+// Update and diagnostics.
+void sg_launch_predict(int64_t n, int64_t ng, double dt, double* x, double* y, double* z,
+                       const double* vx, const double* vy, const double* vz, const double* e,
+                       const double* ax, const double* ay, const double* az, const double* dedt,
+                       double* vtx, double* vty, double* vtz, double* et, hipStream_t st);
+void sg_launch_correct(int64_t n, int64_t ng, double dt, double* vx, double* vy, double* vz,
+                       double* e, const double* vtx, const double* vty, const double* vtz,
+                       const double* et, const double* ax, const double* ay, const double* az,
+                       const double* dedt, hipStream_t st);
+void sg_launch_combine(int64_t n, int64_t ng, const double* asx, const double* asy,
+                       const double* asz, const double* gx, const double* gy, const double* gz,
+                       double* ax, double* ay, double* az, hipStream_t st);
+size_t sg_diag_tmp_bytes();
+void sg_launch_diagnostics(int64_t n, int64_t ng, const double* x, const double* y,
+                           const double* z, const double* vx, const double* vy,
+                           const double* vz, const double* m, const double* e,
+                           const double* pot, double* tmp, double* out10, hipStream_t st);

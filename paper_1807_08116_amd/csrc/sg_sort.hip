@@ -1,0 +1,711 @@
+// sg_sort.hip -- grid sorting of the gas (the SP kernel set of Sec. 3):
+// smoothing-length levels and grid parameters, cell keys, per-cell counts
+// and maximum h, prefix sums for cell offsets, stable reorder and gather of
+// the sorted state.  Also the generic scan used for cell and CSR offsets,
+// and a stable LSD radix sort producing a Morton order of all particles.
+//
+// Built with -ffp-contract=off: the key arithmetic must round exactly like
+// the plain FP64 definition of the grid.
+#include "sg_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline unsigned lane_id() { return threadIdx.x & 63; }
+
+__device__ inline unsigned long long wave_min_u64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// Number of set bits of `mask` below this lane.
+__device__ inline unsigned rank_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// ------------------------------------------------------------------ scan --
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ inline int64_t scan_n(int64_t n_host, const int64_t* n_dev, int64_t cap) {
+    const int64_t n = n_dev ? *n_dev : n_host;
+    return n < cap ? n : cap;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t* __restrict__ in,
+                                                        int64_t n_host,
+                                                        const int64_t* __restrict__ n_dev,
+                                                        int64_t cap,
+                                                        int64_t* __restrict__ bsum) {
+    const int64_t n = scan_n(n_host, n_dev, cap);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k * kBlock + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    s = (int64_t)wave_sum_u64((unsigned long long)s);
+    __shared__ int64_t ws[kBlock / 64];
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += ws[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+// Single block: exclusive scan of the block sums in place; out[n] = total.
+__global__ __launch_bounds__(1024) void k_scan_bsums(int64_t* __restrict__ bsum, int64_t n_host,
+                                                     const int64_t* __restrict__ n_dev,
+                                                     int64_t cap, int64_t* __restrict__ out) {
+    const int64_t n = scan_n(n_host, n_dev, cap);
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    __shared__ int64_t buf[1024];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        int64_t i = c0 + threadIdx.x;
+        int64_t v = i < nb ? bsum[i] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {      // Hillis-Steele inclusive scan
+            int64_t t = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += buf[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t* __restrict__ in,
+                                                      int64_t* __restrict__ out, int64_t n_host,
+                                                      const int64_t* __restrict__ n_dev,
+                                                      int64_t cap,
+                                                      const int64_t* __restrict__ bsum) {
+    const int64_t n = scan_n(n_host, n_dev, cap);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if (base >= n) return;
+    const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t tsum = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (i0 + k < n) ? in[i0 + k] : 0;
+        tsum += v[k];
+    }
+    // exclusive scan of the thread sums across the block
+    int64_t incl = tsum;
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t t = __shfl_up(incl, o, 64);
+        if (lane_id() >= (unsigned)o) incl += t;
+    }
+    __shared__ int64_t wtot[kBlock / 64];
+    if (lane_id() == 63) wtot[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int64_t wbase = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += wtot[w];
+    int64_t run = bsum[blockIdx.x] + wbase + incl - tsum;
+    for (int k = 0; k < kScanItems; ++k) {
+        if (i0 + k < n) out[i0 + k] = run;
+        run += v[k];
+    }
+}
+
+// ------------------------------------------------------------ grid rule --
+
+__device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
+
+// Smallest power of two >= t (t positive and normal).
+__device__ inline double pow2_ceil(double t) {
+    unsigned long long b = (unsigned long long)__builtin_bit_cast(long long, t);
+    unsigned long long mant = b & 0x000fffffffffffffull;
+    if (mant == 0) return t;
+    unsigned long long e = (b >> 52) & 0x7ff;
+    return __builtin_bit_cast(double, (long long)((e + 1) << 52));
+}
+
+// First level l with L0 * 2^l >= h (2 + 2^-9); -1 beyond SG_MAXLEV.
+__device__ inline int level_of(double h, double L0) {
+    double t = h * (2.0 + 0x1p-9);
+    double L = L0;
+    int l = 0;
+    while (L < t) {
+        L *= 2.0;
+        if (++l >= SG_MAXLEV) return -1;
+    }
+    return l;
+}
+
+__global__ void k_status_clear(sg_grid_dev* g) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        g->err = 0;
+        g->need_cells = 0;
+        g->need_nnz = 0;
+    }
+}
+
+__global__ void k_grid_reset(sg_grid_dev* g) {
+    int t = threadIdx.x;
+    if (t == 0) {
+        g->hmin_bits = ~0ull;
+        g->nnz = 0;
+        g->M = 0;
+        g->nlev = 0;
+    }
+    if (t < SG_MAXLEV) {
+        for (int d = 0; d < 3; ++d) {
+            g->lo[t][d] = ~0ull;
+            g->hi[t][d] = 0ull;
+        }
+        g->hmax_bits[t] = 0ull;
+        g->npart[t] = 0ull;
+        g->ncell[t] = 0;
+    }
+    if (t < 3) {
+        g->glo[t] = ~0ull;
+        g->ghi[t] = 0ull;
+    }
+}
+
+// Minimum h and validity of the gas state.
+__global__ __launch_bounds__(kBlock) void k_grid_hmin(const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ z,
+                                                      const double* __restrict__ h, int64_t ng,
+                                                      sg_grid_dev* g) {
+    unsigned long long mn = ~0ull;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ng;
+         i += (int64_t)gridDim.x * kBlock) {
+        double hi = h[i];
+        if (!(hi > 0.0) || !finite_d(hi) || !finite_d(x[i]) || !finite_d(y[i]) || !finite_d(z[i]))
+            bad = true;
+        else {
+            unsigned long long o = sg_ord(hi);
+            mn = o < mn ? o : mn;
+        }
+    }
+    mn = wave_min_u64(mn);
+    if (lane_id() == 0 && mn != ~0ull) atomicMin(&g->hmin_bits, mn);
+    if (bad) atomicOr(&g->err, SGE_NONFINITE);
+}
+
+// Per-level bounding boxes, maximum h and particle counts.
+__global__ __launch_bounds__(kBlock) void k_grid_levels(const double* __restrict__ x,
+                                                        const double* __restrict__ y,
+                                                        const double* __restrict__ z,
+                                                        const double* __restrict__ h,
+                                                        int64_t ng, sg_grid_dev* g) {
+    __shared__ unsigned long long s_lo[SG_MAXLEV][3], s_hi[SG_MAXLEV][3];
+    __shared__ unsigned long long s_hmax[SG_MAXLEV], s_cnt[SG_MAXLEV];
+    if (g->err & SGE_NONFINITE) return;   // uniform across the grid
+    for (int t = threadIdx.x; t < SG_MAXLEV; t += kBlock) {
+        for (int d = 0; d < 3; ++d) {
+            s_lo[t][d] = ~0ull;
+            s_hi[t][d] = 0ull;
+        }
+        s_hmax[t] = 0ull;
+        s_cnt[t] = 0ull;
+    }
+    __syncthreads();
+    const double hmin = sg_unord(g->hmin_bits);
+    const double L0 = pow2_ceil(hmin * (2.0 + 0x1p-9));
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t nround = (ng + stride - 1) / stride;
+    for (int64_t r = 0; r < nround; ++r) {
+        int64_t i = r * stride + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        bool valid = i < ng;
+        int lev = -1;
+        double p[3] = {0, 0, 0}, hi = 0;
+        if (valid) {
+            hi = h[i];
+            p[0] = x[i];
+            p[1] = y[i];
+            p[2] = z[i];
+            lev = level_of(hi, L0);
+            if (lev < 0) {
+                bad = true;
+                valid = false;
+            }
+        }
+        unsigned long long rem = __ballot(valid);
+        while (rem) {
+            int leader = __builtin_ctzll(rem);
+            int L = __shfl(lev, leader, 64);
+            bool mine = valid && lev == L;
+            unsigned long long mm = __ballot(mine);
+            for (int d = 0; d < 3; ++d) {
+                unsigned long long o = mine ? sg_ord(p[d]) : ~0ull;
+                unsigned long long mnv = wave_min_u64(o);
+                unsigned long long mxv = wave_max_u64(mine ? sg_ord(p[d]) : 0ull);
+                if ((int)lane_id() == leader) {
+                    atomicMin(&s_lo[L][d], mnv);
+                    atomicMax(&s_hi[L][d], mxv);
+                }
+            }
+            unsigned long long hm = wave_max_u64(mine ? sg_ord(hi) : 0ull);
+            if ((int)lane_id() == leader) {
+                atomicMax(&s_hmax[L], hm);
+                atomicAdd(&s_cnt[L], (unsigned long long)__builtin_popcountll(mm));
+            }
+            rem &= ~mm;
+        }
+    }
+    if (bad) atomicOr(&g->err, SGE_LEVELS);
+    __syncthreads();
+    for (int t = threadIdx.x; t < SG_MAXLEV; t += kBlock) {
+        if (s_cnt[t] == 0) continue;
+        for (int d = 0; d < 3; ++d) {
+            atomicMin(&g->lo[t][d], s_lo[t][d]);
+            atomicMax(&g->hi[t][d], s_hi[t][d]);
+        }
+        atomicMax(&g->hmax_bits[t], s_hmax[t]);
+        atomicAdd(&g->npart[t], s_cnt[t]);
+    }
+}
+
+__global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (g->err & (SGE_NONFINITE | SGE_LEVELS)) {
+        g->M = 0;
+        return;
+    }
+    const double hmin = sg_unord(g->hmin_bits);
+    const double L0 = pow2_ceil(hmin * (2.0 + 0x1p-9));
+    g->L0 = L0;
+    int nlev = 0;
+    for (int l = 0; l < SG_MAXLEV; ++l)
+        if (g->npart[l]) nlev = l + 1;
+    g->nlev = nlev;
+    int64_t M = 0;
+    double L = L0;
+    for (int l = 0; l < SG_MAXLEV; ++l, L *= 2.0) {
+        g->L[l] = L;
+        g->invL[l] = 1.0 / L;          // exact: L is a power of two
+        g->base[l] = M;
+        g->hmaxlev[l] = g->npart[l] ? sg_unord(g->hmax_bits[l]) : 0.0;
+        if (l >= nlev || g->npart[l] == 0) {
+            g->ncell[l] = 0;
+            for (int d = 0; d < 3; ++d) {
+                g->dim[l][d] = 0;
+                g->org[l][d] = 0.0;
+            }
+            continue;
+        }
+        int64_t nc = 1;
+        for (int d = 0; d < 3; ++d) {
+            double lo = sg_unord(g->lo[l][d]), hi = sg_unord(g->hi[l][d]);
+            double o = floor(lo * g->invL[l]) * L;
+            g->org[l][d] = o;
+            double span = floor((hi - o) * g->invL[l]);
+            if (!(span < 2147483646.0)) {
+                g->err |= SGE_GRID;
+                g->M = 0;
+                return;
+            }
+            g->dim[l][d] = (int64_t)span + 1;
+            nc *= g->dim[l][d];
+            if (nc > 2147483647ll) {
+                g->err |= SGE_GRID;
+                g->M = 0;
+                return;
+            }
+        }
+        g->ncell[l] = nc;
+        M += nc;
+        if (M > 2147483647ll) {
+            g->err |= SGE_GRID;
+            g->M = 0;
+            return;
+        }
+    }
+    g->M = M;
+    if (M > cell_cap) {
+        g->err |= SGE_CELLS;
+        g->need_cells = M;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cells_clear(const sg_grid_dev* g,
+                                                        int32_t* __restrict__ count,
+                                                        unsigned long long* __restrict__ hmax,
+                                                        int32_t* __restrict__ cursor) {
+    if (g->err & SGE_SORT_FATAL) return;
+    const int64_t M = g->M;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < M;
+         k += (int64_t)gridDim.x * kBlock) {
+        count[k] = 0;
+        hmax[k] = 0ull;
+        cursor[k] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys_count(const double* __restrict__ x,
+                                                       const double* __restrict__ y,
+                                                       const double* __restrict__ z,
+                                                       const double* __restrict__ h,
+                                                       int64_t ng, const sg_grid_dev* g,
+                                                       int32_t* __restrict__ key,
+                                                       int32_t* __restrict__ count,
+                                                       unsigned long long* __restrict__ hmax) {
+    if (g->err & SGE_SORT_FATAL) return;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= ng) return;
+    const double hi = h[i];
+    const int l = level_of(hi, g->L0);
+    const double p[3] = {x[i], y[i], z[i]};
+    int64_t c[3];
+    for (int d = 0; d < 3; ++d) {
+        double v = floor((p[d] - g->org[l][d]) * g->invL[l]);
+        double top = (double)(g->dim[l][d] - 1);
+        v = v < 0.0 ? 0.0 : (v > top ? top : v);
+        c[d] = (int64_t)v;
+    }
+    const int32_t k =
+        (int32_t)(g->base[l] + (c[2] * g->dim[l][1] + c[1]) * g->dim[l][0] + c[0]);
+    key[i] = k;
+    atomicAdd(&count[k], 1);
+    atomicMax(&hmax[k], (unsigned long long)__builtin_bit_cast(long long, hi));
+}
+
+// Place particles in their cell's slot range (any order), then fix the order
+// inside each cell to ascending particle id: the rank of particle i in its
+// cell is the number of smaller ids in the same cell range.
+__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ key, int64_t ng,
+                                                    const sg_grid_dev* g,
+                                                    const int64_t* __restrict__ off,
+                                                    int32_t* __restrict__ cursor,
+                                                    int32_t* __restrict__ tmp) {
+    if (g->err & SGE_SORT_FATAL) return;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= ng) return;
+    const int32_t k = key[i];
+    const int64_t slot = off[k] + atomicAdd(&cursor[k], 1);
+    tmp[slot] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rankfix(const int32_t* __restrict__ key, int64_t ng,
+                                                    const sg_grid_dev* g,
+                                                    const int64_t* __restrict__ off,
+                                                    const int32_t* __restrict__ tmp,
+                                                    int32_t* __restrict__ perm) {
+    if (g->err & SGE_SORT_FATAL) return;
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    const int32_t i = tmp[s];
+    const int32_t k = key[i];
+    const int64_t lo = off[k], hi = off[k + 1];
+    int64_t r = 0;
+    for (int64_t t = lo; t < hi; ++t) r += tmp[t] < i;
+    perm[lo + r] = i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_gas(
+    const int32_t* __restrict__ perm, int64_t ng, const sg_grid_dev* g,
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ h, const double* __restrict__ m, double* __restrict__ xs,
+    double* __restrict__ ys, double* __restrict__ zs, double* __restrict__ hs,
+    double* __restrict__ ms) {
+    if (g->err & SGE_SORT_FATAL) return;
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    const int32_t i = perm[s];
+    xs[s] = x[i];
+    ys[s] = y[i];
+    zs[s] = z[i];
+    hs[s] = h[i];
+    ms[s] = m[i];
+}
+
+// ------------------------------------------------------ Morton ordering --
+
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kBlock * kRadixItems;
+
+__global__ void k_gbox_reset(sg_grid_dev* g) {
+    if (threadIdx.x < 3) {
+        g->glo[threadIdx.x] = ~0ull;
+        g->ghi[threadIdx.x] = 0ull;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gbox(const double* __restrict__ x,
+                                                 const double* __restrict__ y,
+                                                 const double* __restrict__ z, int64_t n,
+                                                 sg_grid_dev* g) {
+    unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double p[3] = {x[i], y[i], z[i]};
+        for (int d = 0; d < 3; ++d) {
+            if (!finite_d(p[d])) {
+                bad = true;
+                continue;
+            }
+            unsigned long long o = sg_ord(p[d]);
+            mn[d] = o < mn[d] ? o : mn[d];
+            mx[d] = o > mx[d] ? o : mx[d];
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        unsigned long long a = wave_min_u64(mn[d]), b = wave_max_u64(mx[d]);
+        if (lane_id() == 0) {
+            atomicMin(&g->glo[d], a);
+            atomicMax(&g->ghi[d], b);
+        }
+    }
+    if (bad) atomicOr(&g->err, SGE_NONFINITE);
+}
+
+__device__ inline uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_morton_keys(const double* __restrict__ x,
+                                                        const double* __restrict__ y,
+                                                        const double* __restrict__ z, int64_t n,
+                                                        const sg_grid_dev* g,
+                                                        uint32_t* __restrict__ keys,
+                                                        int32_t* __restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double lo[3], ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = sg_unord(g->glo[d]);
+        double e = sg_unord(g->ghi[d]) - lo[d];
+        ext = e > ext ? e : ext;
+    }
+    const double scale = ext > 0.0 ? 1024.0 / (ext * (1.0 + 0x1p-20)) : 0.0;
+    const double p[3] = {x[i], y[i], z[i]};
+    uint32_t c[3];
+    for (int d = 0; d < 3; ++d) {
+        double v = (p[d] - lo[d]) * scale;
+        v = v < 0.0 ? 0.0 : (v > 1023.0 ? 1023.0 : v);
+        c[d] = (uint32_t)v;
+    }
+    keys[i] = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+    vals[i] = (int32_t)i;
+}
+
+// Digit histogram of one tile, stored digit-major: hist[d * ntiles + tile].
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                       int64_t n, int shift, int64_t ntiles,
+                                                       int32_t* __restrict__ hist) {
+    __shared__ int32_t s_h[256];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int k = 0; k < kRadixItems; ++k) {
+        int64_t i = base + k * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
+}
+
+// Stable scatter: element order inside the tile is preserved within each
+// digit (chunk by chunk, wave by wave, lane by lane).
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
+    int64_t ntiles, const int64_t* __restrict__ offs, uint32_t* __restrict__ kout,
+    int32_t* __restrict__ vout) {
+    __shared__ int32_t s_run[256];
+    __shared__ int32_t s_w[kBlock / 64][256];
+    const int wave = threadIdx.x >> 6;
+    const unsigned lane = lane_id();
+    s_run[threadIdx.x] = 0;
+    for (int w = 0; w < kBlock / 64; ++w) s_w[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int k = 0; k < kRadixItems; ++k) {
+        const int64_t i = base + k * kBlock + threadIdx.x;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const int32_t val = valid ? vin[i] : 0;
+        const uint32_t d = (key >> shift) & 255u;
+        unsigned long long peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            unsigned long long bb = __ballot(valid && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const unsigned r = rank_below(peers);
+        if (valid && r == 0) s_w[wave][d] = __builtin_popcountll(peers);
+        __syncthreads();
+        if (valid) {
+            int32_t pre = 0;
+            for (int w = 0; w < wave; ++w) pre += s_w[w][d];
+            const int64_t dest = offs[(int64_t)d * ntiles + blockIdx.x] + s_run[d] + pre + r;
+            kout[dest] = key;
+            vout[dest] = val;
+        }
+        __syncthreads();
+        int32_t add = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            add += s_w[w][threadIdx.x];
+            s_w[w][threadIdx.x] = 0;
+        }
+        s_run[threadIdx.x] += add;
+        __syncthreads();
+    }
+    (void)lane;
+}
+
+inline unsigned grid_for(int64_t n, int per_block) {
+    int64_t b = (n + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- launchers --
+
+size_t sg_scan_tmp_bytes(int64_t cap) {
+    return sizeof(int64_t) * (size_t)((cap + kScanTile - 1) / kScanTile + 1);
+}
+
+void sg_launch_scan(const int32_t* in, int64_t* out, int64_t n_host, const int64_t* n_dev,
+                    int64_t cap, void* tmp, hipStream_t st) {
+    const unsigned nb = grid_for(cap, kScanTile);
+    int64_t* bsum = (int64_t*)tmp;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, st, in, n_host, n_dev, cap, bsum);
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(1024), 0, st, bsum, n_host, n_dev, cap, out);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, st, in, out, n_host, n_dev, cap,
+                       bsum);
+}
+
+void sg_launch_grid_reset(sg_grid_dev* g, hipStream_t st) {
+    hipLaunchKernelGGL(k_grid_reset, dim3(1), dim3(64), 0, st, g);
+}
+
+void sg_launch_status_clear(sg_grid_dev* g, hipStream_t st) {
+    hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, st, g);
+}
+
+void sg_launch_grid_reduce(const double* x, const double* y, const double* z, const double* h,
+                           int64_t ng, sg_grid_dev* g, hipStream_t st) {
+    unsigned nb = grid_for(ng, kBlock);
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_grid_hmin, dim3(nb), dim3(kBlock), 0, st, x, y, z, h, ng, g);
+    hipLaunchKernelGGL(k_grid_levels, dim3(nb), dim3(kBlock), 0, st, x, y, z, h, ng, g);
+}
+
+void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, hipStream_t st) {
+    hipLaunchKernelGGL(k_grid_finish, dim3(1), dim3(64), 0, st, g, cell_cap);
+}
+
+void sg_launch_cells_clear(sg_grid_dev* g, int32_t* count, unsigned long long* hmax,
+                           int32_t* cursor, int64_t cell_cap, hipStream_t st) {
+    unsigned nb = grid_for(cell_cap, kBlock);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_cells_clear, dim3(nb), dim3(kBlock), 0, st, g, count, hmax, cursor);
+}
+
+void sg_launch_keys_count(const double* x, const double* y, const double* z, const double* h,
+                          int64_t ng, sg_grid_dev* g, int32_t* key, int32_t* count,
+                          unsigned long long* hmax, hipStream_t st) {
+    hipLaunchKernelGGL(k_keys_count, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, st, x, y, z,
+                       h, ng, g, key, count, hmax);
+}
+
+void sg_launch_scatter_rank(const int32_t* key, int64_t ng, const sg_grid_dev* g,
+                            const int64_t* off, int32_t* cursor, int32_t* tmp, int32_t* perm,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, st, key, ng, g,
+                       off, cursor, tmp);
+    hipLaunchKernelGGL(k_rankfix, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, st, key, ng, g,
+                       off, tmp, perm);
+}
+
+void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
+                          const double* x, const double* y, const double* z, const double* h,
+                          const double* m, double* xs, double* ys, double* zs, double* hs,
+                          double* ms, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_gas, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, st, perm, ng,
+                       g, x, y, z, h, m, xs, ys, zs, hs, ms);
+}
+
+// Workspace of the Morton order: two key/value buffers, the digit histogram
+// and its offsets, and the scan scratch.
+static void morton_layout(int64_t n, size_t* o_k1, size_t* o_v0, size_t* o_v1, size_t* o_hist,
+                          size_t* o_offs, size_t* o_scan, size_t* total) {
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    const int64_t nh = 256 * (ntiles > 0 ? ntiles : 1);
+    size_t o = 0;
+    o += al(sizeof(uint32_t) * (size_t)n);  // k0 at 0
+    *o_k1 = o;
+    o += al(sizeof(uint32_t) * (size_t)n);
+    *o_v0 = o;
+    o += al(sizeof(int32_t) * (size_t)n);
+    *o_v1 = o;
+    o += al(sizeof(int32_t) * (size_t)n);
+    *o_hist = o;
+    o += al(sizeof(int32_t) * (size_t)nh);
+    *o_offs = o;
+    o += al(sizeof(int64_t) * (size_t)(nh + 1));
+    *o_scan = o;
+    o += al(sg_scan_tmp_bytes(nh));
+    *total = o;
+}
+
+size_t sg_morton_tmp_bytes(int64_t n) {
+    size_t a, b, c, d, e, f, t;
+    morton_layout(n, &a, &b, &c, &d, &e, &f, &t);
+    return t;
+}
+
+void sg_launch_morton_order(const double* x, const double* y, const double* z, int64_t n,
+                            sg_grid_dev* g, int32_t* order, void* tmp, hipStream_t st) {
+    size_t o_k1, o_v0, o_v1, o_hist, o_offs, o_scan, total;
+    morton_layout(n, &o_k1, &o_v0, &o_v1, &o_hist, &o_offs, &o_scan, &total);
+    char* base = (char*)tmp;
+    uint32_t* k[2] = {(uint32_t*)base, (uint32_t*)(base + o_k1)};
+    int32_t* v[2] = {(int32_t*)(base + o_v0), (int32_t*)(base + o_v1)};
+    int32_t* hist = (int32_t*)(base + o_hist);
+    int64_t* offs = (int64_t*)(base + o_offs);
+    void* scan_tmp = base + o_scan;
+    const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    unsigned nb = grid_for(n, kBlock);
+    hipLaunchKernelGGL(k_gbox_reset, dim3(1), dim3(64), 0, st, g);
+    hipLaunchKernelGGL(k_gbox, dim3(nb > 1024 ? 1024 : nb), dim3(kBlock), 0, st, x, y, z, n, g);
+    hipLaunchKernelGGL(k_morton_keys, dim3(nb), dim3(kBlock), 0, st, x, y, z, n, g, k[0], v[0]);
+    int cur = 0;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kBlock), 0, st, k[cur], n,
+                           shift, ntiles, hist);
+        sg_launch_scan(hist, offs, 256 * ntiles, nullptr, 256 * ntiles, scan_tmp, st);
+        int32_t* vo = (pass == 3) ? order : v[cur ^ 1];
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kBlock), 0, st, k[cur],
+                           v[cur], n, shift, ntiles, offs, k[cur ^ 1], vo);
+        cur ^= 1;
+    }
+}

@@ -1,0 +1,248 @@
+// sg_sph.hip -- SPH sums over the neighbour lists (the paper's DC and HFC
+// kernels, Sec. 3): density (Eq. SPH-mass-density with the cubic spline of
+// Eq. SPH-Kernel), equation of state (Eq. e_p_rho), and the pressure +
+// artificial-viscosity acceleration and energy rate (Eqs. dv_dt-SPH,
+// de_dt-SPH, with the spiky kernel of Eq. SPH-Kernel-p for the gradient).
+//
+// Work is done on the gas gathered into sorted-slot order, so a target's
+// neighbours are close in memory; results are scattered back to particle
+// order.  One thread per target slot walks its CSR row.
+//
+// FP64 form: every pair quantity in FP64.  FP32C form: the FP64 coordinate
+// difference is rounded once to FP32 (cell-relative by construction: it is
+// the difference itself), the rest of the pair arithmetic is FP32 and each
+// sum is Kahan-compensated in FP32; results are returned in FP64.
+#include "sg_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr double kPi = 3.14159265358979323846;
+
+inline unsigned grid_for(int64_t n) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+struct kahan {
+    float s, c;
+    __device__ inline void add(float v) {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ inline double value() const { return (double)s - (double)c; }
+};
+
+// Cubic spline shape (Eq. SPH-Kernel) without the 1/(pi h^3) factor.
+template <typename T>
+__device__ inline T spline_shape(T xi) {
+    if (xi <= T(1)) return T(1) - T(1.5) * xi * xi + T(0.75) * xi * xi * xi;
+    const T t = T(2) - xi;
+    return t > T(0) ? T(0.25) * t * t * t : T(0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_density_f64(sg_sph_bufs b, const sg_grid_dev* g,
+                                                        int64_t ng, double* __restrict__ rho_out) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s], hi = b.hs[s];
+    double acc = b.ms[s] / (kPi * hi * hi * hi);      // self term m_i W(0, h_i)
+    const int64_t e1 = b.nbr_off[s + 1];
+    for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
+        const int32_t t = b.nbr_idx[e];
+        const double dx = xi - b.xs[t], dy = yi - b.ys[t], dz = zi - b.zs[t];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double hij = 0.5 * (hi + b.hs[t]);
+        const double inv = 1.0 / hij;
+        acc += b.ms[t] * spline_shape(r * inv) * (inv * inv * inv) * (1.0 / kPi);
+    }
+    b.rho_s[s] = acc;
+    rho_out[b.perm[s]] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_density_f32(sg_sph_bufs b, const sg_grid_dev* g,
+                                                        int64_t ng, double* __restrict__ rho_out) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s];
+    const float hi = (float)b.hs[s];
+    b.hs_f[s] = hi;
+    b.ms_f[s] = (float)b.ms[s];
+    kahan acc{(float)(b.ms[s] / (kPi * b.hs[s] * b.hs[s] * b.hs[s])), 0.0f};
+    const int64_t e1 = b.nbr_off[s + 1];
+    for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
+        const int32_t t = b.nbr_idx[e];
+        const float dx = (float)(xi - b.xs[t]), dy = (float)(yi - b.ys[t]),
+                    dz = (float)(zi - b.zs[t]);
+        const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+        const float hij = 0.5f * (hi + (float)b.hs[t]);
+        const float inv = 1.0f / hij;
+        acc.add((float)b.ms[t] * spline_shape(r * inv) * (inv * inv * inv) * (float)(1.0 / kPi));
+    }
+    const double rho = acc.value();
+    b.rho_s[s] = rho;
+    rho_out[b.perm[s]] = rho;
+}
+
+// Gather the velocities and energies the force pass should use into slot
+// order and evaluate p / rho^2 and the sound speed sqrt(gamma p / rho).
+__global__ __launch_bounds__(kBlock) void k_sph_prep(sg_sph_bufs b, const sg_grid_dev* g,
+                                                     int64_t ng, int precision, double gamma,
+                                                     const double* __restrict__ vx,
+                                                     const double* __restrict__ vy,
+                                                     const double* __restrict__ vz,
+                                                     const double* __restrict__ e) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    const int32_t i = b.perm[s];
+    const double rho = b.rho_s[s];
+    const double p = (gamma - 1.0) * rho * e[i];
+    const double P = p / (rho * rho);
+    const double c = sqrt(gamma * p / rho);
+    if (precision == SG_FP32C) {
+        b.vx_f[s] = (float)vx[i];
+        b.vy_f[s] = (float)vy[i];
+        b.vz_f[s] = (float)vz[i];
+        b.rho_f[s] = (float)rho;
+        b.P_f[s] = (float)P;
+        b.c_f[s] = (float)c;
+    } else {
+        b.vxs[s] = vx[i];
+        b.vys[s] = vy[i];
+        b.vzs[s] = vz[i];
+        b.P_s[s] = P;
+        b.c_s[s] = c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sph_force_f64(sg_sph_bufs b, const sg_grid_dev* g,
+                                                          int64_t ng, double alpha, double beta,
+                                                          double eta, double* __restrict__ asx,
+                                                          double* __restrict__ asy,
+                                                          double* __restrict__ asz,
+                                                          double* __restrict__ dedt) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s], hi = b.hs[s];
+    const double vxi = b.vxs[s], vyi = b.vys[s], vzi = b.vzs[s];
+    const double Pi_ = b.P_s[s], ci = b.c_s[s], rhoi = b.rho_s[s];
+    const double kgrad = -45.0 / (64.0 * kPi);
+    double sx = 0, sy = 0, sz = 0, se = 0;
+    const int64_t e1 = b.nbr_off[s + 1];
+    for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
+        const int32_t t = b.nbr_idx[e];
+        const double dx = xi - b.xs[t], dy = yi - b.ys[t], dz = zi - b.zs[t];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 == 0.0) continue;                       // coincident pair: no gradient
+        const double r = sqrt(r2);
+        const double hij = 0.5 * (hi + b.hs[t]);
+        const double inv = 1.0 / hij;
+        const double q = 2.0 - r * inv;
+        if (q <= 0.0) continue;
+        const double dvx = vxi - b.vxs[t], dvy = vyi - b.vys[t], dvz = vzi - b.vzs[t];
+        const double rv = dx * dvx + dy * dvy + dz * dvz;
+        double nu = 0.0;
+        if (rv < 0.0) {
+            const double mu = hij * rv / (r2 + eta * hij * hij);
+            nu = mu * (beta * mu - alpha * 0.5 * (ci + b.c_s[t])) / (0.5 * (rhoi + b.rho_s[t]));
+        }
+        const double Pij = Pi_ + b.P_s[t] + nu;
+        // grad W_p = dW_p/dxi * r_ij / (|r_ij| h_ij) = gw * r_ij
+        const double inv2 = inv * inv;
+        const double gw = kgrad * q * q * (inv2 * inv2) / r;
+        const double f = b.ms[t] * Pij * gw;
+        sx -= f * dx;
+        sy -= f * dy;
+        sz -= f * dz;
+        se += f * rv;
+    }
+    const int32_t i = b.perm[s];
+    asx[i] = sx;
+    asy[i] = sy;
+    asz[i] = sz;
+    dedt[i] = 0.5 * se;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const sg_grid_dev* g,
+                                                          int64_t ng, float alpha, float beta,
+                                                          float eta, double* __restrict__ asx,
+                                                          double* __restrict__ asy,
+                                                          double* __restrict__ asz,
+                                                          double* __restrict__ dedt) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s];
+    const float hi = b.hs_f[s];
+    const float vxi = b.vx_f[s], vyi = b.vy_f[s], vzi = b.vz_f[s];
+    const float Pi_ = b.P_f[s], ci = b.c_f[s], rhoi = b.rho_f[s];
+    const float kgrad = (float)(-45.0 / (64.0 * kPi));
+    kahan sx{0, 0}, sy{0, 0}, sz{0, 0}, se{0, 0};
+    const int64_t e1 = b.nbr_off[s + 1];
+    for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
+        const int32_t t = b.nbr_idx[e];
+        const float dx = (float)(xi - b.xs[t]), dy = (float)(yi - b.ys[t]),
+                    dz = (float)(zi - b.zs[t]);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 == 0.0f) continue;
+        const float r = sqrtf(r2);
+        const float hij = 0.5f * (hi + b.hs_f[t]);
+        const float inv = 1.0f / hij;
+        const float q = 2.0f - r * inv;
+        if (q <= 0.0f) continue;
+        const float dvx = vxi - b.vx_f[t], dvy = vyi - b.vy_f[t], dvz = vzi - b.vz_f[t];
+        const float rv = dx * dvx + dy * dvy + dz * dvz;
+        float nu = 0.0f;
+        if (rv < 0.0f) {
+            const float mu = hij * rv / (r2 + eta * hij * hij);
+            nu = mu * (beta * mu - alpha * 0.5f * (ci + b.c_f[t])) / (0.5f * (rhoi + b.rho_f[t]));
+        }
+        const float Pij = Pi_ + b.P_f[t] + nu;
+        const float inv2 = inv * inv;
+        const float gw = kgrad * q * q * (inv2 * inv2) / r;
+        const float f = b.ms_f[t] * Pij * gw;
+        sx.add(-f * dx);
+        sy.add(-f * dy);
+        sz.add(-f * dz);
+        se.add(f * rv);
+    }
+    const int32_t i = b.perm[s];
+    asx[i] = sx.value();
+    asy[i] = sy.value();
+    asz[i] = sz.value();
+    dedt[i] = 0.5 * se.value();
+}
+
+}  // namespace
+
+void sg_launch_density(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
+                       double* rho_out, hipStream_t st) {
+    if (precision == SG_FP32C)
+        hipLaunchKernelGGL(k_density_f32, dim3(grid_for(ng)), dim3(kBlock), 0, st, b, g, ng, rho_out);
+    else
+        hipLaunchKernelGGL(k_density_f64, dim3(grid_for(ng)), dim3(kBlock), 0, st, b, g, ng, rho_out);
+}
+
+void sg_launch_sph_prep(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
+                        double gamma, const double* vx, const double* vy, const double* vz,
+                        const double* e, hipStream_t st) {
+    hipLaunchKernelGGL(k_sph_prep, dim3(grid_for(ng)), dim3(kBlock), 0, st, b, g, ng, precision,
+                       gamma, vx, vy, vz, e);
+}
+
+void sg_launch_sph_force(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
+                         double alpha, double beta, double eta, double* asx, double* asy,
+                         double* asz, double* dedt, hipStream_t st) {
+    if (precision == SG_FP32C)
+        hipLaunchKernelGGL(k_sph_force_f32, dim3(grid_for(ng)), dim3(kBlock), 0, st, b, g, ng,
+                           (float)alpha, (float)beta, (float)eta, asx, asy, asz, dedt);
+    else
+        hipLaunchKernelGGL(k_sph_force_f64, dim3(grid_for(ng)), dim3(kBlock), 0, st, b, g, ng,
+                           alpha, beta, eta, asx, asy, asz, dedt);
+}

@@ -1,0 +1,72 @@
+"""The C ABI on the host: the library loads, exports every entry point the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sg():
+    from paper_1807_08116_amd import sphgrav
+    sphgrav.lib()
+    return sphgrav
+
+
+def test_header_symbols_exported(sg):
+    hdr = open(os.path.join(ROOT, "include", "sphgrav.h")).read()
+    declared = set(re.findall(r"\b(sg_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(sg.EXPORTED)
+    L = sg.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_struct_sizes_match_header(sg):
+    # sg_params: 6 doubles + 8 int32; sg_caps: 4 int64; sg_state: 15 pointers
+    assert C.sizeof(sg.Params) == 6 * 8 + 8 * 4
+    assert C.sizeof(sg.Caps) == 32
+    assert C.sizeof(sg.State) == 15 * 8
+    assert C.sizeof(sg.GridInfo) == 8 + 8 + 16 * 8 * (1 + 3 + 1 + 1 + 1 + 1) + 16 * 8 * 3 + 8
+
+
+def test_workspace_validation(sg):
+    caps = sg.default_caps(1000, 1000)
+    good = sg.make_params()
+    assert sg.workspace_bytes(good, caps) > 0
+    for bad in (dict(eps=0.0), dict(eps=-1.0), dict(gamma=1.0), dict(alpha=-1.0),
+                dict(eta=0.0), dict(precision=7), dict(grav_ipl=3), dict(grav_split=65),
+                dict(G=float("nan"))):
+        assert sg.workspace_bytes(sg.make_params(**bad), caps) == 0, bad
+    p = sg.make_params()
+    p.reserved[2] = 1
+    assert sg.workspace_bytes(p, caps) == 0
+    assert sg.workspace_bytes(good, sg.Caps(0, 0, 0, 0)) == 0
+    assert sg.workspace_bytes(good, sg.Caps(-1, 5, 5, 5)) == 0
+    assert sg.workspace_bytes(good, sg.Caps(10, 0, 0, 10)) == 0      # gas without cells
+    # halo-only needs no cells or lists
+    assert sg.workspace_bytes(good, sg.Caps(0, 10, 0, 0)) > 0
+    # the FP32C form needs its extra mirrors
+    assert sg.workspace_bytes(sg.make_params(precision=sg.SG_FP32C), caps) > \
+        sg.workspace_bytes(good, caps)
+
+
+def test_create_rejects_before_device(sg):
+    L = sg.lib()
+    p, c = sg.make_params(), sg.default_caps(100, 100)
+    h = C.c_void_p()
+    need = sg.workspace_bytes(p, c)
+    assert L.sg_create(C.byref(p), C.byref(c), None, need, None, C.byref(h)) == sg.SG_EINVAL
+    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x1001), need, None, C.byref(h)) == sg.SG_EINVAL
+    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x100000), need - 1, None,
+                       C.byref(h)) == sg.SG_EINVAL
+    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x100000), need, None, None) == sg.SG_EINVAL
+    assert h.value is None
+    assert L.sg_bind_state(None, 1, 1, None) == sg.SG_EINVAL
+    assert L.sg_build_neighbors(None) == sg.SG_EINVAL
+    assert L.sg_sync(None, None) == sg.SG_EINVAL
+    assert L.sg_last_error(None) == b"null context"
+    assert L.sg_version().startswith(b"sphgrav")

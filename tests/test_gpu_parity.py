@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer outputs (keys, counts, offsets, per-cell hmax, permutation,
+neighbour CSR) must match bit for bit.  FP64 results must match to a
+normwise relative error of 1e-12 (only summation order differs; the
+FP64 reciprocal square root is refined to rounding level).  The FP32C
+form must stay within the 1e-6 acceleration target.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32C_TOL = 1e-6
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def sg():
+    _need_gpu()
+    from paper_1807_08116_amd import sphgrav
+    sphgrav.lib()
+    return sphgrav
+
+
+def nrm_err(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.sum(b * b)
+    return float(np.sqrt(np.sum((a - b) ** 2) / den)) if den > 0 else float(np.sqrt(np.sum(a * a)))
+
+
+def oracle_sort_and_rows(orc, st):
+    ng = st["ng"]
+    x, y, z = st["x"][:ng], st["y"][:ng], st["z"][:ng]
+    s = orc.sort_gas(x, y, z, st["h"])
+    nb = orc.nbrs(x, y, z, st["h"])
+    soff, sidx = orc.rows_to_slots(s["perm"], *nb)
+    return s, nb, soff, sidx
+
+
+def check_sort_bitexact(sg, eng, s, soff, sidx, orc):
+    ctx = eng.ctx
+    np.testing.assert_array_equal(ctx.export(sg.SG_X_KEYS), s["key"])
+    np.testing.assert_array_equal(ctx.export(sg.SG_X_COUNTS), s["count"])
+    np.testing.assert_array_equal(ctx.export(sg.SG_X_OFFSETS), s["off"])
+    np.testing.assert_array_equal(ctx.export(sg.SG_X_HMAX), s["hmax"])
+    np.testing.assert_array_equal(ctx.export(sg.SG_X_PERM), s["perm"])
+    np.testing.assert_array_equal(ctx.export(sg.SG_X_NBR_OFF), soff)
+    np.testing.assert_array_equal(ctx.export(sg.SG_X_NBR_IDX), sidx)
+    gd = sg.grid_dict(ctx.export(sg.SG_X_GRID))
+    od = orc.grid_dict(s["grid"])
+    for k in ("L0", "nlev", "M"):
+        assert gd[k] == od[k], k
+    for k in ("L", "org", "dim", "base", "ncell", "npart", "hmax"):
+        np.testing.assert_array_equal(gd[k], od[k], err_msg=k)
+
+
+def full_eval(eng, sg):
+    eng.build_neighbors()
+    eng.ctx.compute_density()
+    eng.ctx.compute_accel(sg.SG_SPH | sg.SG_GRAV | sg.SG_POT)
+    eng.ctx.sync()
+
+
+def oracle_accel(orc, st, ref):
+    ax, ay, az = orc.total_accel(st, ref)
+    return np.stack([ax, ay, az], 1)
+
+
+def gpu_accel(eng):
+    return np.stack([eng.numpy("ax"), eng.numpy("ay"), eng.numpy("az")], 1)
+
+
+# --------------------------------------------------------------- c0 size --
+
+@pytest.fixture(scope="module")
+def c0():
+    from paper_1807_08116_amd import ic
+    return ic.make("c0")
+
+
+@pytest.fixture(scope="module")
+def c0_ref(c0, orc):
+    from paper_1807_08116_amd import ic
+    ref = orc.forces(c0, ic.DEFAULT_PARAMS)
+    s, nb, soff, sidx = oracle_sort_and_rows(orc, c0)
+    return ref, s, soff, sidx
+
+
+def test_c0_sort_and_neighbours_bitexact(sg, orc, c0, c0_ref):
+    ref, s, soff, sidx = c0_ref
+    eng = sg.Engine(c0, precision=sg.SG_FP64)
+    eng.build_neighbors()
+    check_sort_bitexact(sg, eng, s, soff, sidx, orc)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_c0_forces(sg, orc, c0, c0_ref, precision):
+    ref, s, soff, sidx = c0_ref
+    p = sg.SG_FP64 if precision == "fp64" else sg.SG_FP32C
+    tol = FP64_TOL if precision == "fp64" else FP32C_TOL
+    eng = sg.Engine(c0, precision=p)
+    full_eval(eng, sg)
+    ng = c0["ng"]
+    # neighbour lists do not depend on the precision form
+    np.testing.assert_array_equal(eng.ctx.export(sg.SG_X_NBR_IDX), sidx)
+    e_rho = nrm_err(eng.numpy("rho")[:ng], ref["rho"])
+    e_acc = nrm_err(gpu_accel(eng), oracle_accel(orc, c0, ref))
+    e_de = nrm_err(eng.numpy("dedt")[:ng], ref["dedt"])
+    e_pot = nrm_err(eng.numpy("pot"), ref["pot"])
+    print(precision, "rho", e_rho, "acc", e_acc, "dedt", e_de, "pot", e_pot)
+    assert e_rho < tol and e_acc < tol and e_de < (tol if p == sg.SG_FP64 else 1e-5)
+    assert e_pot < tol
+
+
+@pytest.mark.parametrize("ipl,split", [(1, 1), (2, 3), (4, 1), (1, 64), (4, 7)])
+def test_gravity_launch_shapes(sg, orc, c0, c0_ref, ipl, split):
+    ref, *_ = c0_ref
+    for p in (sg.SG_FP64, sg.SG_FP32C):
+        eng = sg.Engine(c0, precision=p, grav_ipl=ipl, grav_split=split)
+        eng.ctx.compute_accel(sg.SG_GRAV | sg.SG_POT)
+        eng.ctx.sync()
+        g = np.stack([ref["gx"], ref["gy"], ref["gz"]], 1)
+        tol = FP64_TOL if p == sg.SG_FP64 else FP32C_TOL
+        assert nrm_err(gpu_accel(eng), g) < tol
+        assert nrm_err(eng.numpy("pot"), ref["pot"]) < tol
+
+
+def test_c0_step_matches_oracle(sg, orc, c0):
+    from paper_1807_08116_amd import ic
+    prm = ic.DEFAULT_PARAMS
+    dt = 2e-3
+    eng = sg.Engine(c0, precision=sg.SG_FP64)
+    st, cache = c0, None
+    for _ in range(2):
+        eng.ctx.step(dt, sg.SG_POT)
+        st, cache = orc.pc_step(st, prm, dt, cache)
+    eng.ctx.sync()
+    for f in ("x", "y", "z", "vx", "vy", "vz"):
+        assert nrm_err(eng.numpy(f), st[f]) < 1e-12, f
+    assert nrm_err(eng.numpy("e")[:st["ng"]], st["e"]) < 1e-12
+
+
+def test_diagnostics(sg, orc, c0, c0_ref):
+    ref, *_ = c0_ref
+    import torch
+    eng = sg.Engine(c0, precision=sg.SG_FP64)
+    full_eval(eng, sg)
+    d = eng.ctx.diagnostics().cpu().numpy()
+    o = orc.diagnostics(c0["x"], c0["y"], c0["z"], c0["vx"], c0["vy"], c0["vz"], c0["m"],
+                        c0["e"], ref["pot"], c0["ng"])
+    scale = np.array([o[0], o[1], abs(o[2]), abs(o[3])] + [np.sum(c0["m"] * 0.1)] * 3
+                     + [np.sum(c0["m"]) * 0.3] * 3)
+    assert np.all(np.abs(d - o) <= 1e-12 * scale + 1e-18), (d, o)
+    del torch
+
+
+def test_determinism(sg, c0):
+    outs = []
+    for _ in range(2):
+        eng = sg.Engine(c0, precision=sg.SG_FP32C)
+        full_eval(eng, sg)
+        eng.ctx.step(1e-3, sg.SG_POT)
+        eng.ctx.sync()
+        outs.append([eng.numpy(f).copy() for f in ("x", "vx", "ax", "rho", "dedt", "pot")])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
+# ------------------------------------------------------------ edge cases --
+
+def _random_state(rng, ng, nh, dup=0):
+    n = ng + nh
+    pos = rng.normal(size=(n, 3))
+    if dup and ng > dup:
+        pos[1:dup + 1] = pos[0]
+    st = {"ng": ng, "x": pos[:, 0].copy(), "y": pos[:, 1].copy(), "z": pos[:, 2].copy(),
+          "vx": rng.normal(size=n) * 0.1, "vy": rng.normal(size=n) * 0.1,
+          "vz": rng.normal(size=n) * 0.1, "m": rng.uniform(0.5, 1.5, n) / n,
+          "e": rng.uniform(0.02, 0.08, ng), "h": rng.uniform(0.1, 0.4, ng) * (1 + np.abs(pos[:ng, 0]))}
+    return st
+
+
+@pytest.mark.parametrize("ng,nh,dup", [(1, 0, 0), (2, 0, 0), (0, 3, 0), (1000, 777, 0),
+                                       (257, 0, 5), (3000, 1, 40), (64, 4097, 0)])
+def test_edge_sizes(sg, orc, ng, nh, dup):
+    from paper_1807_08116_amd import ic
+    rng = np.random.default_rng(ng * 7919 + nh)
+    st = _random_state(rng, ng, nh, dup)
+    eng = sg.Engine(st, precision=sg.SG_FP64)
+    full_eval(eng, sg)
+    ref = orc.forces(st, ic.DEFAULT_PARAMS)
+    if ng > 0:
+        s, nb, soff, sidx = oracle_sort_and_rows(orc, st)
+        check_sort_bitexact(sg, eng, s, soff, sidx, orc)
+        assert nrm_err(eng.numpy("rho")[:ng], ref["rho"]) < FP64_TOL
+    assert nrm_err(gpu_accel(eng), oracle_accel(orc, st, ref)) < FP64_TOL
+    eng32 = sg.Engine(st, precision=sg.SG_FP32C)
+    full_eval(eng32, sg)
+    assert nrm_err(gpu_accel(eng32), oracle_accel(orc, st, ref)) < 1e-5
+
+
+def test_capacity_overflow_and_retry(sg, orc, c0, c0_ref):
+    ref, s, soff, sidx = c0_ref
+    caps = sg.default_caps(c0["ng"], len(c0["x"]) - c0["ng"], cell_cap=10, nnz_cap=100)
+    eng = sg.Engine(c0, precision=sg.SG_FP64, caps=caps)
+    eng.ctx.build_neighbors()
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.sync()
+    assert ei.value.code == sg.SG_ECAPACITY
+    assert ei.value.need[0] == s["grid"].M
+    eng.build_neighbors()                      # grows the workspace and retries
+    np.testing.assert_array_equal(eng.ctx.export(sg.SG_X_NBR_IDX), sidx)
+
+
+def test_bad_inputs_reported(sg):
+    rng = np.random.default_rng(11)
+    st = _random_state(rng, 100, 10)
+    st["h"][5] = 0.0
+    eng = sg.Engine(st, precision=sg.SG_FP64)
+    eng.ctx.build_neighbors()
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.sync()
+    assert ei.value.code == sg.SG_ENONFINITE
+    st = _random_state(rng, 100, 10)
+    st["x"][3] = np.nan
+    eng = sg.Engine(st, precision=sg.SG_FP64)
+    eng.ctx.build_neighbors()
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.sync()
+    assert ei.value.code == sg.SG_ENONFINITE
+    st = _random_state(rng, 100, 10)
+    st["h"][7] = 1e6                            # > 2^16 times the smallest h
+    st["h"][8] = 1e-3
+    eng = sg.Engine(st, precision=sg.SG_FP64)
+    eng.ctx.build_neighbors()
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.sync()
+    assert ei.value.code == sg.SG_ERANGE
+
+
+def test_call_order_errors(sg, c0):
+    eng = sg.Engine(c0, precision=sg.SG_FP64)
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.compute_density()
+    assert ei.value.code == sg.SG_ESTATE
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.kick_drift(1e-3, sg.SG_CORRECT)
+    assert ei.value.code == sg.SG_ESTATE
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.compute_accel(sg.SG_POT)
+    assert ei.value.code == sg.SG_EINVAL
