@@ -31,6 +31,22 @@ PEAK = {"fp32": 157.3, "fp64": 78.6}  # TFLOP/s, MI355X vector peaks
 DT = 1e-3
 
 
+def recorded_traffic(precision_form):
+    """HBM bytes per gravity launch from committed rocprofv3 counter runs, or
+    None when the kernel source changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gravity_%s_c2_traffic.json" % precision_form)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, rec["kernel_source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["kernel_source_sha256"]:
+            return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def nrm_err(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
 
@@ -123,6 +139,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only", choices=["fp32c", "fp64", "both"], default="both")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
@@ -183,7 +201,8 @@ def main():
                                "+ FP64 energy/momentum sums" % (args.config, ng, n - ng),
                    "n_particles": n, "n_gas": ng, "precision_form": head, "seed": ic.SEED_BASE + int(args.config[1:])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": recorded_traffic(head) if args.config == "c2" else None,
                      "kernel": "gravity pair kernel (%s), %d flops/pair x N^2 per launch, "
                                "%.1f ms/launch" % (head, FLOPS_PER_PAIR, 1e3 * grav_s)},
         "cpu_baseline": cpu,
@@ -202,6 +221,14 @@ def main():
         }
     if "fp64" in res and "fp32c" in res:
         out["fp32c_vs_fp64_speedup"] = res["fp64"]["sec"] / res["fp32c"]["sec"]
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": 1 << 30, "write": 1 << 30, "launches": 3}
     print(json.dumps(out), flush=True)
 
 
