@@ -55,9 +55,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(sg, st, precision, steps, warmup, sample):
+def run_form(sg, st, precision, steps, warmup, sample, tune):
     import torch
-    eng = sg.Engine(st, precision=precision)
+    eng = sg.Engine(st, precision=precision, **tune)
     ctx = eng.ctx
     # force evaluation at t = 0 (for the error check against the oracle)
     eng.build_neighbors()
@@ -139,6 +139,9 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only", choices=["fp32c", "fp64", "both"], default="both")
+    ap.add_argument("--ipl", type=int, default=0, help="gravity targets per lane (0 = auto)")
+    ap.add_argument("--split", type=int, default=0, help="gravity source splits (0 = auto)")
+    ap.add_argument("--variant", type=int, default=0, help="FP64 rsqrt seed (0 FP32, 1 FP64)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -165,7 +168,8 @@ def main():
     for form in forms:
         p = sg.SG_FP32C if form == "fp32c" else sg.SG_FP64
         log("timing %s: %d warmup + %d steps" % (form, args.warmup, args.steps))
-        res[form] = run_form(sg, st, p, args.steps, args.warmup, sample)
+        tune = dict(grav_ipl=args.ipl, grav_split=args.split, grav_variant=args.variant)
+        res[form] = run_form(sg, st, p, args.steps, args.warmup, sample, tune)
         log("  %s: %.3f s/step" % (form, res[form]["sec"] / args.steps))
 
     cpu = None

@@ -73,13 +73,17 @@ typedef enum {
  * precision: an sg_precision value.
  * grav_ipl: target particles per GPU lane in the gravity kernel (1, 2 or 4;
  *   0 = automatic).  grav_split: number of source-range splits (>= 1;
- *   0 = automatic).  Neither changes results beyond summation order. */
+ *   0 = automatic).  Neither changes results beyond summation order.
+ * grav_variant (FP64 form): 0 = reciprocal square root seeded in FP32 and
+ *   refined in FP64 (needs eps^2 >= 1.2e-38), 1 = seeded in FP64; both are
+ *   refined to FP64 rounding level. */
 typedef struct {
     double G, eps, gamma, alpha, beta, eta;
     int32_t precision;
     int32_t grav_ipl;
     int32_t grav_split;
-    int32_t reserved[5];        /* must be zero */
+    int32_t grav_variant;
+    int32_t reserved[4];        /* must be zero */
 } sg_params;
 
 /* Capacities the workspace is sized for.
@@ -162,6 +166,32 @@ sg_status sg_kick_drift(sg_ctx *ctx, double dt, int32_t phase);
  * -> SG_CORRECT.  flags may add SG_POT. */
 sg_status sg_step(sg_ctx *ctx, double dt, uint32_t flags);
 
+/* nsteps whole steps (as sg_step) with the conserved quantities of each
+ * step written to d_hist[10*k .. 10*k+9] (device, may be NULL).  With
+ * use_graph != 0, the first step runs eagerly and the steady-state step
+ * (step + diagnostics) is captured once into a HIP graph and replayed for
+ * the remaining steps (dt is fixed inside the graph; stage timing must be
+ * off).  Results are identical to nsteps calls of sg_step.  Waits for the
+ * stream before returning. */
+sg_status sg_run(sg_ctx *ctx, double dt, int64_t nsteps, uint32_t flags, int32_t use_graph,
+                 double *d_hist);
+
+/* Time step of Eq. (dt-stability) at the current state into *d_dt (device
+ * double): C min_i s_i / (cmax_i (1 + 1.2 alpha) + 1.2 beta mumax_i
+ * + sqrt(s_i (|Q_i| + |E_i|))) over gas particles with neighbours, with
+ * s_i = min_j |r_ij|, cmax_i = max_j (c_i + c_j)/2, mumax_i = max_j |mu_ij|
+ * (mu_ij <= 0 by its definition, so its magnitude is taken), Q_i the total
+ * acceleration and E_i = de_i/dt (the square-root term as printed).  +inf
+ * if no particle has a neighbour.  Needs neighbours, density and
+ * accelerations at the current state (sg_compute_accel with SG_SPH|SG_GRAV,
+ * outside a predict/correct pair).  Always FP64. */
+sg_status sg_cfl_dt(sg_ctx *ctx, double C, double *d_dt);
+
+/* Smoothing-length update h_i = sigma (m_i / rho_i)^{1/3} (Sec. 2.2) into
+ * st->h from the last density.  Invalidates neighbour lists, density and
+ * forces. */
+sg_status sg_update_h(sg_ctx *ctx, double sigma);
+
 /* Conserved quantities into d_out10 (device, 10 doubles): E_kin, E_int,
  * E_pot (needs SG_POT computed), E_total, momentum (3), angular momentum
  * (3); FP64 sums in a fixed order. */
@@ -224,7 +254,8 @@ typedef enum {
 sg_status sg_profile_enable(sg_ctx *ctx, int32_t on);
 sg_status sg_profile_read(sg_ctx *ctx, double ms[SG_NSTAGE], int64_t count[SG_NSTAGE]);
 
-/* Last error message of this context (static storage; never NULL). */
+/* Last error message of this context; with ctx == NULL, the reason the
+ * calling thread's last sg_create() failed.  Never NULL. */
 const char *sg_last_error(const sg_ctx *ctx);
 
 /* Destroy the context (does not free the workspace or the state). */

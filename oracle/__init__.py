@@ -120,6 +120,10 @@ def lib():
         L.or_correct.argtypes = [_i64, _i64, _dbl] + [_D] * 12
         L.or_diagnostics.restype = None
         L.or_diagnostics.argtypes = [_i64, _i64] + [_D] * 8 + [_opt(_D), _D]
+        L.or_cfl_dt.restype = _dbl
+        L.or_cfl_dt.argtypes = [_i64] + [_D] * 12 + [_dbl] * 4 + [_I64, _I32]
+        L.or_update_h.restype = None
+        L.or_update_h.argtypes = [_i64, _dbl, _D, _D, _D]
         L.or_max_levels.restype = C.c_int
         L.or_grid_size.restype = C.c_size_t
         assert L.or_max_levels() == MAX_LEVELS
@@ -318,6 +322,21 @@ def diagnostics(x, y, z, vx, vy, vz, m, e, pot, ng):
     lib().or_diagnostics(n, int(ng), _c(x), _c(y), _c(z), _c(vx), _c(vy), _c(vz), _c(m),
                          _c(e) if ng > 0 else np.zeros(1), None if pot is None else _c(pot), out)
     return out
+
+
+def cfl_dt(x, y, z, vx, vy, vz, h, c, qx, qy, qz, E, C, alpha, beta, eta, off, idx):
+    """Eq. (dt-stability) over the gas rows (see or_cfl_dt)."""
+    n = len(x)
+    return lib().or_cfl_dt(n, _c(x), _c(y), _c(z), _c(vx), _c(vy), _c(vz), _c(h), _c(c),
+                           _c(qx), _c(qy), _c(qz), _c(E), float(C), float(alpha), float(beta),
+                           float(eta), _c(off, np.int64), _c(idx, np.int32))
+
+
+def update_h(m, rho, sigma):
+    n = len(m)
+    h = np.empty(n)
+    lib().or_update_h(n, float(sigma), _c(m), _c(rho), h)
+    return h
 
 
 # --------------------------------------------------------------------------

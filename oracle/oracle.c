@@ -611,5 +611,63 @@ void or_diagnostics(int64_t n, int64_t ng, const double *x, const double *y,
     out[3] = out[0] + out[1] + out[2];
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* Step control (Sec. 2.2)                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. (dt-stability): dt = C min_i s_i / (cmax_i (1 + 1.2 alpha)
+ *   + 1.2 beta mumax_i + sqrt(s_i (|Q_i| + |E_i|))), over gas particles with
+ * at least one neighbour, where s_i = min_j |r_ij|, cmax_i = max_j c_ij,
+ * c_ij = (c_i + c_j)/2 and mumax_i = max_j |mu_ij| (mu_ij as in the
+ * viscosity; it is never positive, so its largest magnitude is taken).
+ * Q_i is the total acceleration and E_i = de_i/dt.  The square-root term is
+ * used as printed (its two parts carry different units).  Returns +inf when
+ * no particle has a neighbour. */
+double or_cfl_dt(int64_t ng, const double *x, const double *y, const double *z,
+                 const double *vx, const double *vy, const double *vz, const double *h,
+                 const double *c, const double *qx, const double *qy, const double *qz,
+                 const double *E, double C, double alpha, double beta, double eta,
+                 const int64_t *off, const int32_t *idx)
+{
+    double best = INFINITY;
+    for (int64_t i = 0; i < ng; i++) {
+        if (off[i + 1] == off[i])
+            continue;
+        double smin = INFINITY, cmax = 0.0, mumax = 0.0;
+        for (int64_t k = off[i]; k < off[i + 1]; k++) {
+            int32_t j = idx[k];
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            double r = sqrt(r2);
+            if (r < smin)
+                smin = r;
+            double cij = 0.5 * (c[i] + c[j]);
+            if (cij > cmax)
+                cmax = cij;
+            double rv = dx * (vx[i] - vx[j]) + dy * (vy[i] - vy[j]) + dz * (vz[i] - vz[j]);
+            if (rv < 0.0) {
+                double hij = 0.5 * (h[i] + h[j]);
+                double mu = fabs(hij * rv / (r2 + eta * hij * hij));
+                if (mu > mumax)
+                    mumax = mu;
+            }
+        }
+        double q = sqrt(qx[i] * qx[i] + qy[i] * qy[i] + qz[i] * qz[i]);
+        double den = cmax * (1.0 + 1.2 * alpha) + 1.2 * beta * mumax + sqrt(smin * (q + fabs(E[i])));
+        double dt = den > 0.0 ? smin / den : INFINITY;
+        if (dt < best)
+            best = dt;
+    }
+    return C * best;
+}
+
+/* h_i = sigma (m_i / rho_i)^(1/3) (Sec. 2.2, after Eq. SPH-Kernel). */
+void or_update_h(int64_t ng, double sigma, const double *m, const double *rho, double *h)
+{
+    for (int64_t i = 0; i < ng; i++)
+        h[i] = sigma * cbrt(m[i] / rho[i]);
+}
+
 int or_max_levels(void) { return OR_MAX_LEVELS; }
 size_t or_grid_size(void) { return sizeof(or_grid_t); }

@@ -11,6 +11,8 @@
 
 namespace {
 
+thread_local char g_create_msg[256] = "null context";
+
 constexpr size_t kAlign = 256;
 inline size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -33,7 +35,7 @@ struct layout {
     size_t gorder, morton, gsorted;
     size_t part;
     size_t vtx, vty, vtz, et;
-    size_t diag;
+    size_t diag, diag_out;
     size_t total;
 };
 
@@ -81,6 +83,7 @@ layout make_layout(const sg_params* p, const sg_caps* c) {
     L.vtz = take(8 * n);
     L.et = take(8 * ng);
     L.diag = take(sg_diag_tmp_bytes());
+    L.diag_out = take(10 * sizeof(double));
     L.total = o;
     return L;
 }
@@ -99,6 +102,10 @@ bool params_ok(const sg_params* p, const char** why) {
     if (p->grav_ipl != 0 && p->grav_ipl != 1 && p->grav_ipl != 2 && p->grav_ipl != 4)
         return *why = "grav_ipl must be 0, 1, 2 or 4", false;
     if (p->grav_split < 0 || p->grav_split > 64) return *why = "grav_split must be in [0, 64]", false;
+    if (p->grav_variant < 0 || p->grav_variant > 1)
+        return *why = "grav_variant must be 0 or 1", false;
+    if (p->precision == SG_FP64 && p->grav_variant == 0 && !(p->eps * p->eps >= 1.2e-38))
+        return *why = "FP32-seeded FP64 gravity needs eps^2 in the FP32 normal range", false;
     for (int r : p->reserved)
         if (r != 0) return *why = "reserved fields must be zero", false;
     return true;
@@ -226,6 +233,10 @@ namespace {
 sg_status need_bound(sg_ctx* c) {
     if (!c) return SG_EINVAL;
     if (!c->bound) return c->fail(SG_ESTATE, "no state bound (call sg_bind_state)");
+    // The runtime's last-error slot is per thread and may hold an error left
+    // by another library's earlier call; clear it so that the checks after
+    // this entry point's launches see only their own errors.
+    (void)hipGetLastError();
     return SG_OK;
 }
 
@@ -316,6 +327,7 @@ sg_status do_gravity(sg_ctx* c, bool pot) {
     a.precision = c->prm.precision;
     grav_shape(c, &a.ipl, &a.split);
     a.with_pot = pot ? 1 : 0;
+    a.variant = c->prm.grav_variant;
     a.order = nullptr;
     a.sorted = c->at<void>(c->L.gsorted);
     a.gx = c->at<double>(c->L.gx);
@@ -429,6 +441,38 @@ sg_status do_kick_drift(sg_ctx* c, double dt, int phase) {
     return c->check_launch("kick/drift");
 }
 
+
+sg_status do_step(sg_ctx* c, double dt, uint32_t flags) {
+    sg_status r;
+    if (flags & ~SG_POT) return c->fail(SG_EINVAL, "steps accept only SG_POT");
+    if (!__builtin_isfinite(dt)) return c->fail(SG_EINVAL, "dt must be finite");
+    if (c->predicted) return c->fail(SG_ESTATE, "step inside a predict/correct pair");
+    const uint32_t gflags = SG_GRAV | (flags & SG_POT);
+    // forces at r(t): neighbours and density are reused from the previous
+    // step's corrector (positions unchanged since), gravity likewise.
+    if (!c->have_nbr && (r = do_build(c)) != SG_OK) return r;
+    if (!c->have_rho && (r = do_density(c)) != SG_OK) return r;
+    if (!c->have_grav || ((flags & SG_POT) && !c->have_pot))
+        if ((r = do_gravity(c, (flags & SG_POT) != 0)) != SG_OK) return r;
+    if ((r = do_sph(c)) != SG_OK) return r;                 // predictor right-hand side
+    do_combine(c);
+    if ((r = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return r;
+    if ((r = do_build(c)) != SG_OK) return r;
+    if ((r = do_density(c)) != SG_OK) return r;
+    if ((r = do_accel(c, gflags | SG_SPH)) != SG_OK) return r;   // corrector right-hand side
+    return do_kick_drift(c, dt, SG_CORRECT);
+}
+
+sg_status do_diag(sg_ctx* c, double* d_out10) {
+    const double* pot = nullptr;
+    if (c->have_pot) pot = c->s.pot ? c->s.pot : c->at<double>(c->L.gpot);
+    c->begin(SG_ST_DIAG);
+    sg_launch_diagnostics(c->n, c->ng, c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.m,
+                          c->s.e, pot, c->at<double>(c->L.diag), d_out10, c->st);
+    c->end();
+    return c->check_launch("diagnostics");
+}
+
 }  // namespace
 
 extern "C" {
@@ -444,10 +488,19 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
     if (!out) return SG_EINVAL;
     *out = nullptr;
     const char* why = nullptr;
-    if (!params_ok(prm, &why) || !caps_ok(caps, &why)) return SG_EINVAL;
-    if (!d_workspace || ((uintptr_t)d_workspace & (kAlign - 1))) return SG_EINVAL;
+    if (!params_ok(prm, &why) || !caps_ok(caps, &why)) {
+        snprintf(g_create_msg, sizeof(g_create_msg), "%s", why ? why : "invalid arguments");
+        return SG_EINVAL;
+    }
+    if (!d_workspace || ((uintptr_t)d_workspace & (kAlign - 1))) {
+        snprintf(g_create_msg, sizeof(g_create_msg), "workspace must be 256-byte aligned, non-null");
+        return SG_EINVAL;
+    }
     layout L = make_layout(prm, caps);
-    if (ws_bytes < L.total) return SG_EINVAL;
+    if (ws_bytes < L.total) {
+        snprintf(g_create_msg, sizeof(g_create_msg), "workspace smaller than sg_workspace_bytes()");
+        return SG_EINVAL;
+    }
     sg_ctx* c = new (std::nothrow) sg_ctx();
     if (!c) return SG_EINVAL;
     c->prm = *prm;
@@ -469,9 +522,11 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
         c->prof_ms[k] = 0.0;
         c->prof_n[k] = 0;
     }
+    (void)hipGetLastError();            // drop a stale error of an earlier call
     sg_launch_status_clear(c->grid(), c->st);
     sg_launch_grid_reset(c->grid(), c->st);
     if (c->check_launch("create") != SG_OK) {
+        snprintf(g_create_msg, sizeof(g_create_msg), "%s", c->msg);
         delete c;
         return SG_EDEVICE;
     }
@@ -481,6 +536,7 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
 
 sg_status sg_bind_state(sg_ctx* c, int64_t n_gas, int64_t n_halo, const sg_state* st) {
     if (!c) return SG_EINVAL;
+    (void)hipGetLastError();
     if (!st) return c->fail(SG_EINVAL, "state is NULL");
     if (n_gas < 0 || n_halo < 0 || n_gas + n_halo < 1)
         return c->fail(SG_EINVAL, "need n_gas, n_halo >= 0 and at least one particle");
@@ -530,37 +586,88 @@ sg_status sg_kick_drift(sg_ctx* c, double dt, int32_t phase) {
 
 sg_status sg_step(sg_ctx* c, double dt, uint32_t flags) {
     sg_status r = need_bound(c);
+    return r != SG_OK ? r : do_step(c, dt, flags);
+}
+
+sg_status sg_run(sg_ctx* c, double dt, int64_t nsteps, uint32_t flags, int32_t use_graph,
+                 double* d_hist) {
+    sg_status r = need_bound(c);
     if (r != SG_OK) return r;
-    if (flags & ~SG_POT) return c->fail(SG_EINVAL, "sg_step accepts only SG_POT");
-    if (!__builtin_isfinite(dt)) return c->fail(SG_EINVAL, "dt must be finite");
-    if (c->predicted) return c->fail(SG_ESTATE, "sg_step inside a predict/correct pair");
-    const uint32_t gflags = SG_GRAV | (flags & SG_POT);
-    // forces at r(t): neighbours and density are reused from the previous
-    // step's corrector (positions unchanged since), gravity likewise.
-    if (!c->have_nbr && (r = do_build(c)) != SG_OK) return r;
-    if (!c->have_rho && (r = do_density(c)) != SG_OK) return r;
-    if (!c->have_grav || ((flags & SG_POT) && !c->have_pot))
-        if ((r = do_gravity(c, (flags & SG_POT) != 0)) != SG_OK) return r;
-    if ((r = do_sph(c)) != SG_OK) return r;                 // predictor right-hand side
-    do_combine(c);
-    if ((r = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return r;
-    if ((r = do_build(c)) != SG_OK) return r;
-    if ((r = do_density(c)) != SG_OK) return r;
-    if ((r = do_accel(c, gflags | SG_SPH)) != SG_OK) return r;   // corrector right-hand side
-    return do_kick_drift(c, dt, SG_CORRECT);
+    if (nsteps < 0) return c->fail(SG_EINVAL, "nsteps must be >= 0");
+    if (use_graph && c->prof) return c->fail(SG_ESTATE, "stage timing must be off to capture a graph");
+    double* diag = c->at<double>(c->L.diag_out);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (use_graph && k == 1) break;
+        if ((r = do_step(c, dt, flags)) != SG_OK) return r;
+        if (d_hist && (r = do_diag(c, d_hist + 10 * k)) != SG_OK) return r;
+    }
+    if (!use_graph || nsteps < 2) return hipStreamSynchronize(c->st) == hipSuccess
+                                              ? SG_OK : c->fail(SG_EDEVICE, "stream sync failed");
+    // steady state reached: capture one step (+ diagnostics into a fixed slot)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(c->st, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return c->fail(SG_EDEVICE, "hipStreamBeginCapture failed");
+    sg_status rc = do_step(c, dt, flags);
+    if (rc == SG_OK && d_hist) rc = do_diag(c, diag);
+    hipError_t ec = hipStreamEndCapture(c->st, &graph);
+    if (rc != SG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ec != hipSuccess || !graph) return c->fail(SG_EDEVICE, "hipStreamEndCapture failed");
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return c->fail(SG_EDEVICE, "hipGraphInstantiate failed");
+    }
+    for (int64_t k = 1; k < nsteps && rc == SG_OK; ++k) {
+        if (hipGraphLaunch(exec, c->st) != hipSuccess) rc = c->fail(SG_EDEVICE, "hipGraphLaunch failed");
+        else if (d_hist && hipMemcpyAsync(d_hist + 10 * k, diag, 10 * sizeof(double),
+                                          hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+            rc = c->fail(SG_EDEVICE, "history copy failed");
+    }
+    if (hipStreamSynchronize(c->st) != hipSuccess && rc == SG_OK)
+        rc = c->fail(SG_EDEVICE, "stream sync failed");
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return rc;
+}
+
+sg_status sg_cfl_dt(sg_ctx* c, double C, double* d_dt) {
+    sg_status r = need_bound(c);
+    if (r != SG_OK) return r;
+    if (!d_dt || ((uintptr_t)d_dt & 7)) return c->fail(SG_EINVAL, "d_dt must be an aligned device pointer");
+    if (!(C > 0.0) || !__builtin_isfinite(C)) return c->fail(SG_EINVAL, "C must be > 0");
+    if (c->ng == 0) return c->fail(SG_ESTATE, "the time-step rule needs gas particles");
+    if (c->predicted) return c->fail(SG_ESTATE, "time step inside a predict/correct pair");
+    if (!c->have_rho || !c->have_grav || !c->have_sph)
+        return c->fail(SG_ESTATE, "time step needs neighbours, density and accelerations");
+    sg_sph_bufs b = c->sph();
+    // sound speeds and velocities of the current state, FP64, slot order
+    sg_launch_sph_prep(b, c->grid(), c->ng, SG_FP64, c->prm.gamma, c->s.vx, c->s.vy, c->s.vz,
+                       c->s.e, c->st);
+    sg_launch_cfl(b, c->grid(), c->ng, c->prm.alpha, c->prm.beta, c->prm.eta, C, c->s.ax, c->s.ay,
+                  c->s.az, c->s.dedt, d_dt, c->st);
+    return c->check_launch("time step");
+}
+
+sg_status sg_update_h(sg_ctx* c, double sigma) {
+    sg_status r = need_bound(c);
+    if (r != SG_OK) return r;
+    if (!(sigma > 0.0) || !__builtin_isfinite(sigma)) return c->fail(SG_EINVAL, "sigma must be > 0");
+    if (c->predicted) return c->fail(SG_ESTATE, "h update inside a predict/correct pair");
+    if (c->ng == 0) return SG_OK;
+    if (!c->have_rho) return c->fail(SG_ESTATE, "h update needs the density");
+    sg_launch_update_h(c->sph(), c->grid(), c->ng, sigma, c->s.h, c->st);
+    c->invalidate_positions();     // lists, density and forces depend on h
+    return c->check_launch("h update");
 }
 
 sg_status sg_diagnostics(sg_ctx* c, double* d_out10) {
     sg_status r = need_bound(c);
     if (r != SG_OK) return r;
     if (!d_out10) return c->fail(SG_EINVAL, "output is NULL");
-    const double* pot = nullptr;
-    if (c->have_pot) pot = c->s.pot ? c->s.pot : c->at<double>(c->L.gpot);
-    c->begin(SG_ST_DIAG);
-    sg_launch_diagnostics(c->n, c->ng, c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.m,
-                          c->s.e, pot, c->at<double>(c->L.diag), d_out10, c->st);
-    c->end();
-    return c->check_launch("diagnostics");
+    return do_diag(c, d_out10);
 }
 
 sg_status sg_export(sg_ctx* c, int32_t what, void* dst, int64_t cap_bytes, int64_t* n_out) {
@@ -640,10 +747,11 @@ sg_status sg_sync(sg_ctx* c, int64_t need[2]) {
     return SG_ECAPACITY;
 }
 
-const char* sg_last_error(const sg_ctx* c) { return c ? c->msg : "null context"; }
+const char* sg_last_error(const sg_ctx* c) { return c ? c->msg : g_create_msg; }
 
 sg_status sg_profile_enable(sg_ctx* c, int32_t on) {
     if (!c) return SG_EINVAL;
+    (void)hipGetLastError();
     if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(SG_EDEVICE, "stream sync failed");
     for (auto& mk : c->marks) {
         c->pool.push_back(mk.a);

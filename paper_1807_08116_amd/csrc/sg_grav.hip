@@ -33,8 +33,13 @@ struct alignas(16) d4 {
     double x, y, z, w;
 };
 
+// SEED32: start from the FP32 reciprocal square root of (float)r2 (relative
+// error below 2^-23, on the transcendental pipe, which runs beside the main
+// vector ALU) instead of the FP64 one (below 2^-24, a quarter-rate slot on
+// the main ALU); r2 must then lie in the normal FP32 range (r2 >= eps^2).
+template <bool SEED32>
 __device__ inline double rsqrt_f64(double r2) {
-    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double y0 = SEED32 ? (double)__builtin_amdgcn_rsqf((float)r2) : __builtin_amdgcn_rsq(r2);
     const double t = r2 * y0;
     const double e = __builtin_fma(-t, y0, 1.0);
     const double p = __builtin_fma(e, 0.375, 0.5);
@@ -42,7 +47,7 @@ __device__ inline double rsqrt_f64(double r2) {
     return __builtin_fma(u, p, y0);
 }
 
-template <int IPL, bool POT>
+template <int IPL, bool POT, bool SEED32>
 __global__ __launch_bounds__(kBlock) void k_grav_f64(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const double* __restrict__ m, int64_t n, int64_t jchunk, double eps2, double G,
@@ -86,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_grav_f64(
             for (int k = 0; k < IPL; ++k) {
                 const double dx = q.x - xi[k], dy = q.y - yi[k], dz = q.z - zi[k];
                 const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
-                const double rinv = rsqrt_f64(r2);
+                const double rinv = rsqrt_f64<SEED32>(r2);
                 const double mr = q.w * rinv;
                 const double s = mr * (rinv * rinv);
                 ax[k] = __builtin_fma(s, dx, ax[k]);
@@ -382,8 +387,12 @@ void launch_t(const sg_grav_args& a, dim3 grid, int64_t jchunk, int final_out, d
                            a.ms, (const box6*)a.sbox, a.order, a.n, jchunk,
                            (float)(a.eps * a.eps), a.G, inv_eps, final_out, ox, oy, oz, op,
                            ostride);
+    else if (a.variant == 1)
+        hipLaunchKernelGGL((k_grav_f64<IPL, POT, false>), grid, dim3(kBlock), 0, st, a.x, a.y, a.z,
+                           a.m, a.n, jchunk, a.eps * a.eps, a.G, inv_eps, final_out, ox, oy, oz,
+                           op, ostride);
     else
-        hipLaunchKernelGGL((k_grav_f64<IPL, POT>), grid, dim3(kBlock), 0, st, a.x, a.y, a.z,
+        hipLaunchKernelGGL((k_grav_f64<IPL, POT, true>), grid, dim3(kBlock), 0, st, a.x, a.y, a.z,
                            a.m, a.n, jchunk, a.eps * a.eps, a.G, inv_eps, final_out, ox, oy, oz,
                            op, ostride);
 }

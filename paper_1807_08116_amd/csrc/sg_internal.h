@@ -115,12 +115,20 @@ void sg_launch_sph_force(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng,
                          double alpha, double beta, double eta, double* asx, double* asy,
                          double* asz, double* dedt, hipStream_t st);
 
+// Step control: CFL time step into *out (device double) and h update.
+void sg_launch_cfl(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, double alpha,
+                   double beta, double eta, double C, const double* qx, const double* qy,
+                   const double* qz, const double* dedt, double* out, hipStream_t st);
+void sg_launch_update_h(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, double sigma,
+                        double* h, hipStream_t st);
+
 // Gravity.
 struct sg_grav_args {
     const double *x, *y, *z, *m;
     int64_t n;
     double G, eps;
     int precision, ipl, split, with_pot;
+    int variant;                        // FP64: 0 = FP32-seeded rsqrt, 1 = FP64-seeded
     const int32_t* order;               // FP32C: Morton order of the particles, else null
     void* sorted;                       // FP32C: scratch of sg_grav_sorted_bytes(n)
     const double *xs, *ys, *zs, *ms;    // (set by the launcher) sorted copies

@@ -219,6 +219,75 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const s
     dedt[i] = 0.5 * se.value();
 }
 
+
+// Step control of Sec. 2.2.  CFL bound of Eq. (dt-stability) per gas slot,
+// reduced to the minimum over slots with at least one neighbour: positive
+// doubles order like their bit patterns, so an integer atomic min is exact
+// and order-independent.
+__global__ void k_cfl_init(unsigned long long* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = 0x7ff0000000000000ull;   // +inf
+}
+
+__global__ __launch_bounds__(kBlock) void k_cfl(sg_sph_bufs b, const sg_grid_dev* g, int64_t ng,
+                                                double alpha, double beta, double eta,
+                                                const double* __restrict__ qx,
+                                                const double* __restrict__ qy,
+                                                const double* __restrict__ qz,
+                                                const double* __restrict__ dedt,
+                                                unsigned long long* __restrict__ out) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double dt = __builtin_inf();
+    if (s < ng && b.nbr_off[s + 1] > b.nbr_off[s]) {
+        const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s], hi = b.hs[s];
+        const double vxi = b.vxs[s], vyi = b.vys[s], vzi = b.vzs[s], ci = b.c_s[s];
+        double smin = __builtin_inf(), cmax = 0.0, mumax = 0.0;
+        for (int64_t e = b.nbr_off[s]; e < b.nbr_off[s + 1]; ++e) {
+            const int32_t t = b.nbr_idx[e];
+            const double dx = xi - b.xs[t], dy = yi - b.ys[t], dz = zi - b.zs[t];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double r = sqrt(r2);
+            smin = r < smin ? r : smin;
+            const double cij = 0.5 * (ci + b.c_s[t]);
+            cmax = cij > cmax ? cij : cmax;
+            const double rv = dx * (vxi - b.vxs[t]) + dy * (vyi - b.vys[t]) + dz * (vzi - b.vzs[t]);
+            if (rv < 0.0) {
+                const double hij = 0.5 * (hi + b.hs[t]);
+                const double mu = fabs(hij * rv / (r2 + eta * hij * hij));
+                mumax = mu > mumax ? mu : mumax;
+            }
+        }
+        const int32_t i = b.perm[s];
+        const double q = sqrt(qx[i] * qx[i] + qy[i] * qy[i] + qz[i] * qz[i]);
+        const double den = cmax * (1.0 + 1.2 * alpha) + 1.2 * beta * mumax +
+                           sqrt(smin * (q + fabs(dedt[i])));
+        if (den > 0.0) dt = smin / den;
+    }
+    unsigned long long v = (unsigned long long)__builtin_bit_cast(long long, dt);
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMin(out, v);
+}
+
+__global__ void k_cfl_final(unsigned long long* out, double C) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double v = __builtin_bit_cast(double, (long long)*out);
+        *(double*)out = C * v;
+    }
+}
+
+// h_i = sigma (m_i / rho_i)^{1/3} (Sec. 2.2, after Eq. SPH-Kernel).
+__global__ __launch_bounds__(kBlock) void k_update_h(sg_sph_bufs b, const sg_grid_dev* g,
+                                                     int64_t ng, double sigma,
+                                                     double* __restrict__ h) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    h[b.perm[s]] = sigma * cbrt(b.ms[s] / b.rho_s[s]);
+}
+
 }  // namespace
 
 void sg_launch_density(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
@@ -245,4 +314,19 @@ void sg_launch_sph_force(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng,
     else
         hipLaunchKernelGGL(k_sph_force_f64, dim3(grid_for(ng)), dim3(kBlock), 0, st, b, g, ng,
                            alpha, beta, eta, asx, asy, asz, dedt);
+}
+
+void sg_launch_cfl(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, double alpha,
+                   double beta, double eta, double C, const double* qx, const double* qy,
+                   const double* qz, const double* dedt, double* out, hipStream_t st) {
+    unsigned long long* o = (unsigned long long*)out;
+    hipLaunchKernelGGL(k_cfl_init, dim3(1), dim3(64), 0, st, o);
+    hipLaunchKernelGGL(k_cfl, dim3(grid_for(ng)), dim3(kBlock), 0, st, b, g, ng, alpha, beta, eta,
+                       qx, qy, qz, dedt, o);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, o, C);
+}
+
+void sg_launch_update_h(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, double sigma,
+                        double* h, hipStream_t st) {
+    hipLaunchKernelGGL(k_update_h, dim3(grid_for(ng)), dim3(kBlock), 0, st, b, g, ng, sigma, h);
 }

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "SG_OK", 1: "SG_EINVAL", 2: "SG_ECAPACITY", 3: "SG_EDEVICE", 
 
 # Every entry point declared in include/sphgrav.h.
 EXPORTED = ["sg_workspace_bytes", "sg_create", "sg_bind_state", "sg_build_neighbors",
-            "sg_compute_density", "sg_compute_accel", "sg_kick_drift", "sg_step",
+            "sg_compute_density", "sg_compute_accel", "sg_kick_drift", "sg_step", "sg_run", "sg_cfl_dt", "sg_update_h",
             "sg_diagnostics", "sg_export", "sg_sync", "sg_profile_enable", "sg_profile_read",
             "sg_last_error", "sg_destroy", "sg_version"]
 STAGES = ["sort", "nbr", "density", "sph", "grav_prep", "grav", "update", "diag"]
@@ -47,7 +47,7 @@ class Params(C.Structure):
     _fields_ = [("G", C.c_double), ("eps", C.c_double), ("gamma", C.c_double),
                 ("alpha", C.c_double), ("beta", C.c_double), ("eta", C.c_double),
                 ("precision", C.c_int32), ("grav_ipl", C.c_int32), ("grav_split", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("grav_variant", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Caps(C.Structure):
@@ -72,6 +72,10 @@ class GridInfo(C.Structure):
 
 
 _lib = None
+
+
+def C_void(t):
+    return C.c_void_p(t.data_ptr())
 
 
 def lib():
@@ -99,6 +103,12 @@ def lib():
     L.sg_kick_drift.argtypes = [vp, dbl, i32]
     L.sg_step.restype = C.c_int
     L.sg_step.argtypes = [vp, dbl, u32]
+    L.sg_run.restype = C.c_int
+    L.sg_run.argtypes = [vp, dbl, i64, u32, i32, vp]
+    L.sg_cfl_dt.restype = C.c_int
+    L.sg_cfl_dt.argtypes = [vp, dbl, vp]
+    L.sg_update_h.restype = C.c_int
+    L.sg_update_h.argtypes = [vp, dbl]
     L.sg_diagnostics.restype = C.c_int
     L.sg_diagnostics.argtypes = [vp, vp]
     L.sg_export.restype = C.c_int
@@ -120,8 +130,8 @@ def lib():
 
 
 def make_params(G=1.0, eps=0.01, gamma=5.0 / 3.0, alpha=1.0, beta=2.0, eta=0.1,
-                precision=SG_FP64, grav_ipl=0, grav_split=0):
-    return Params(G, eps, gamma, alpha, beta, eta, precision, grav_ipl, grav_split)
+                precision=SG_FP64, grav_ipl=0, grav_split=0, grav_variant=0):
+    return Params(G, eps, gamma, alpha, beta, eta, precision, grav_ipl, grav_split, grav_variant)
 
 
 def default_caps(n_gas, n_halo, cell_cap=None, nnz_cap=None):
@@ -156,12 +166,16 @@ class Context:
         self.ws_bytes = nbytes
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
+        elif stream == "new":
+            # a stream of its own (default priority): needed for graph capture
+            stream = torch.cuda.Stream(device=self.device)
+        torch.cuda.synchronize(self.device)     # state uploads on other streams are done
         self.stream = stream
         h = C.c_void_p()
         rc = L.sg_create(C.byref(params), C.byref(caps), C.c_void_p(self.ws_ptr),
                          C.c_size_t(nbytes), C.c_void_p(stream.cuda_stream), C.byref(h))
         if rc != SG_OK:
-            raise SGError(rc, "sg_create failed")
+            raise SGError(rc, "sg_create failed: " + L.sg_last_error(None).decode())
         self.h = h
         self.state = None
 
@@ -207,6 +221,26 @@ class Context:
 
     def step(self, dt, flags=0):
         self._check(lib().sg_step(self.h, float(dt), flags), "sg_step")
+
+    def run(self, dt, nsteps, flags=0, use_graph=True, hist=None):
+        """nsteps steps (graph-replayed after the first when use_graph);
+        returns the [nsteps, 10] device tensor of per-step diagnostics."""
+        if hist is None:
+            hist = self.torch.empty((max(nsteps, 1), 10), dtype=self.torch.float64,
+                                    device=self.device)
+        self._check(lib().sg_run(self.h, float(dt), int(nsteps), flags, 1 if use_graph else 0,
+                                 C.c_void_p(hist.data_ptr())), "sg_run")
+        return hist
+
+    def cfl_dt(self, C=0.5, out=None):
+        """Eq. (dt-stability) time step at the current state (device tensor)."""
+        if out is None:
+            out = self.torch.empty(1, dtype=self.torch.float64, device=self.device)
+        self._check(lib().sg_cfl_dt(self.h, float(C), C_void(out)), "sg_cfl_dt")
+        return out
+
+    def update_h(self, sigma):
+        self._check(lib().sg_update_h(self.h, float(sigma)), "sg_update_h")
 
     def diagnostics(self, out=None):
         if out is None:
@@ -304,7 +338,7 @@ class Engine:
     """Convenience owner of a context plus a bound state, with capacity retry."""
 
     def __init__(self, st: dict, precision=SG_FP64, device="cuda", params=None, caps=None,
-                 with_pot=True, **kw):
+                 with_pot=True, stream=None, **kw):
         self.ng = int(st["ng"])
         self.n = len(st["x"])
         self.nh = self.n - self.ng
@@ -312,10 +346,13 @@ class Engine:
         self.caps = caps if caps is not None else default_caps(self.ng, self.nh)
         self.dev = to_device(st, device, with_pot=with_pot)
         self.device = device
+        self.stream = stream
         self._make()
 
     def _make(self):
-        self.ctx = Context(self.params, self.caps, self.device)
+        self.ctx = Context(self.params, self.caps, self.device, stream=self.stream)
+        if self.stream == "new":
+            self.stream = self.ctx.stream
         self.ctx.bind_state(self.dev, self.ng, self.nh)
 
     def grow(self, need):
@@ -339,4 +376,5 @@ class Engine:
         raise SGError(SG_ECAPACITY, "could not size the workspace")
 
     def numpy(self, name):
+        self.ctx.torch.cuda.synchronize()
         return self.dev[name].cpu().numpy()

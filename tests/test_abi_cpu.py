@@ -39,7 +39,7 @@ def test_workspace_validation(sg):
     assert sg.workspace_bytes(good, caps) > 0
     for bad in (dict(eps=0.0), dict(eps=-1.0), dict(gamma=1.0), dict(alpha=-1.0),
                 dict(eta=0.0), dict(precision=7), dict(grav_ipl=3), dict(grav_split=65),
-                dict(G=float("nan"))):
+                dict(G=float("nan")), dict(grav_variant=2), dict(eps=1e-20)):
         assert sg.workspace_bytes(sg.make_params(**bad), caps) == 0, bad
     p = sg.make_params()
     p.reserved[2] = 1
@@ -65,8 +65,9 @@ def test_create_rejects_before_device(sg):
                        C.byref(h)) == sg.SG_EINVAL
     assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x100000), need, None, None) == sg.SG_EINVAL
     assert h.value is None
+    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x1001), need, None, C.byref(h)) == sg.SG_EINVAL
     assert L.sg_bind_state(None, 1, 1, None) == sg.SG_EINVAL
     assert L.sg_build_neighbors(None) == sg.SG_EINVAL
     assert L.sg_sync(None, None) == sg.SG_EINVAL
-    assert L.sg_last_error(None) == b"null context"
+    assert b"aligned" in L.sg_last_error(None)         # reason of the last failed create
     assert L.sg_version().startswith(b"sphgrav")

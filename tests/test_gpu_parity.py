@@ -120,11 +120,12 @@ def test_c0_forces(sg, orc, c0, c0_ref, precision):
     assert e_pot < tol
 
 
-@pytest.mark.parametrize("ipl,split", [(1, 1), (2, 3), (4, 1), (1, 64), (4, 7)])
-def test_gravity_launch_shapes(sg, orc, c0, c0_ref, ipl, split):
+@pytest.mark.parametrize("ipl,split,variant", [(1, 1, 0), (2, 3, 1), (4, 1, 0), (4, 1, 1),
+                                               (1, 64, 0), (4, 7, 1)])
+def test_gravity_launch_shapes(sg, orc, c0, c0_ref, ipl, split, variant):
     ref, *_ = c0_ref
     for p in (sg.SG_FP64, sg.SG_FP32C):
-        eng = sg.Engine(c0, precision=p, grav_ipl=ipl, grav_split=split)
+        eng = sg.Engine(c0, precision=p, grav_ipl=ipl, grav_split=split, grav_variant=variant)
         eng.ctx.compute_accel(sg.SG_GRAV | sg.SG_POT)
         eng.ctx.sync()
         g = np.stack([ref["gx"], ref["gy"], ref["gz"]], 1)
@@ -257,3 +258,32 @@ def test_call_order_errors(sg, c0):
     with pytest.raises(sg.SGError) as ei:
         eng.ctx.compute_accel(sg.SG_POT)
     assert ei.value.code == sg.SG_EINVAL
+
+
+# ----------------------------------------------------------- step control --
+
+def test_cfl_dt_and_h_update(sg, orc, c0, c0_ref):
+    from paper_1807_08116_amd import ic
+    prm = ic.DEFAULT_PARAMS
+    ref, s, soff, sidx = c0_ref
+    ng = c0["ng"]
+    eng = sg.Engine(c0, precision=sg.SG_FP64)
+    full_eval(eng, sg)
+    dt = eng.ctx.cfl_dt(0.6).cpu().numpy()[0]
+    ax, ay, az = orc.total_accel(c0, ref)
+    p, c = orc.eos(ref["rho"], c0["e"], prm["gamma"])
+    x, y, z = c0["x"][:ng], c0["y"][:ng], c0["z"][:ng]
+    odt = orc.cfl_dt(x, y, z, c0["vx"][:ng], c0["vy"][:ng], c0["vz"][:ng], c0["h"], c,
+                     ax[:ng], ay[:ng], az[:ng], ref["dedt"], 0.6, prm["alpha"], prm["beta"],
+                     prm["eta"], *ref["nb"])
+    assert abs(dt / odt - 1) < 1e-12, (dt, odt)
+    eng.ctx.update_h(1.25)
+    eng.ctx.sync()
+    hn = orc.update_h(c0["m"][:ng], ref["rho"], 1.25)
+    assert nrm_err(eng.numpy("h")[:ng], hn) < 1e-14
+    # lists are rebuilt from the new h on the next call
+    with pytest.raises(sg.SGError):
+        eng.ctx.compute_density()
+    eng.build_neighbors()
+    eng.ctx.compute_density()
+    eng.ctx.sync()

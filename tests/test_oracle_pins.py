@@ -403,3 +403,50 @@ def test_diagnostics_closed_form(orc):
     pot = np.array([-0.5, -0.5])
     d = orc.diagnostics(x, y, z, vx, vy, vz, m, e, pot, 1)
     np.testing.assert_allclose(d, [1.0, 0.25, -0.5, 0.75, 0, 0, 0, 0, 0, 2.0], atol=1e-15)
+
+
+# --------------------------------------------------------- step control ----
+
+def test_cfl_lattice_at_rest_closed_form(orc):
+    # Eq. (dt-stability) on a lattice at rest with no forces: s_i = d, all
+    # c_ij = c, mu = 0, Q = E = 0, so dt = C d / (c (1 + 1.2 alpha)).
+    n, d = 6, 0.1
+    x, y, z = _lattice(n, d)
+    N = len(x)
+    h = np.full(N, 0.75 * d)
+    off, idx = orc.nbrs_brute(x, y, z, h)
+    c = np.full(N, 0.3)
+    zero = np.zeros(N)
+    for C, alpha in ((0.5, 1.0), (0.8, 0.5)):
+        dt = orc.cfl_dt(x, y, z, zero, zero, zero, h, c, zero, zero, zero, zero, C, alpha, 2.0,
+                        0.1, off, idx)
+        assert abs(dt - C * d / (0.3 * (1 + 1.2 * alpha))) < 1e-15
+    # an acceleration and a compressive pair can only shorten the step
+    q = np.zeros(N)
+    q[5] = 4.0
+    v = np.zeros(N)
+    v[7] = 1.0
+    dt0 = orc.cfl_dt(x, y, z, zero, zero, zero, h, c, zero, zero, zero, zero, 0.5, 1, 2, 0.1, off, idx)
+    dt1 = orc.cfl_dt(x, y, z, zero, zero, zero, h, c, q, zero, zero, zero, 0.5, 1, 2, 0.1, off, idx)
+    dt2 = orc.cfl_dt(x, y, z, v, zero, zero, h, c, zero, zero, zero, zero, 0.5, 1, 2, 0.1, off, idx)
+    assert dt1 < dt0 and dt2 < dt0
+    # no neighbours at all: no constraint
+    far = np.arange(3) * 10.0
+    o1, i1 = orc.nbrs_brute(far, far * 0, far * 0, np.full(3, 0.1))
+    assert orc.cfl_dt(far, far * 0, far * 0, *([np.zeros(3)] * 3), np.full(3, 0.1), np.ones(3),
+                      *([np.zeros(3)] * 4), 0.5, 1, 2, 0.1, o1, i1) == float("inf")
+
+
+def test_h_update_lattice(orc):
+    # h = sigma (m/rho)^(1/3): on a lattice rho -> m/d^3, so h -> sigma d.
+    n, d = 13, 0.1
+    x, y, z = _lattice(n, d)
+    N = len(x)
+    m = np.full(N, d ** 3)
+    h = np.full(N, 1.5 * d)
+    off, idx = orc.nbrs_brute(x, y, z, h)
+    rho = orc.density(x, y, z, m, h, off, idx)
+    hn = orc.update_h(m, rho, 1.25)
+    c = (n // 2) * n * n + (n // 2) * n + n // 2
+    assert abs(hn[c] / (1.25 * d) - 1) < 1e-3
+    assert np.all(orc.update_h(m, rho, 2.5) == 2 * hn)          # linear in sigma
