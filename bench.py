@@ -141,7 +141,9 @@ def main():
     ap.add_argument("--only", choices=["fp32c", "fp64", "both"], default="both")
     ap.add_argument("--ipl", type=int, default=0, help="gravity targets per lane (0 = auto)")
     ap.add_argument("--split", type=int, default=0, help="gravity source splits (0 = auto)")
-    ap.add_argument("--variant", type=int, default=0, help="FP64 rsqrt seed (0 FP32, 1 FP64)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="gravity kernel: 0 automatic; FP64 1 FP32-seeded rsqrt, 2 FP64-seeded; "
+                         "FP32C 1 vector ALU, 2 matrix-core far field")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()

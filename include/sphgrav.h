@@ -74,9 +74,12 @@ typedef enum {
  * grav_ipl: target particles per GPU lane in the gravity kernel (1, 2 or 4;
  *   0 = automatic).  grav_split: number of source-range splits (>= 1;
  *   0 = automatic).  Neither changes results beyond summation order.
- * grav_variant (FP64 form): 0 = reciprocal square root seeded in FP32 and
- *   refined in FP64 (needs eps^2 >= 1.2e-38), 1 = seeded in FP64; both are
- *   refined to FP64 rounding level. */
+ * grav_variant: 0 = automatic.  FP64 form: 1 = reciprocal square root
+ *   seeded in FP32 and refined in FP64 (needs eps^2 >= 1.2e-38; the
+ *   automatic choice), 2 = seeded in FP64 (both refined to FP64 rounding
+ *   level).  FP32C form: 1 = all pairs on the vector ALU (the automatic
+ *   choice), 2 = far-field squared separations on the matrix cores (MFMA;
+ *   required by ensembles). */
 typedef struct {
     double G, eps, gamma, alpha, beta, eta;
     int32_t precision;
@@ -234,6 +237,29 @@ sg_status sg_export(sg_ctx *ctx, int32_t what, void *d_dst, int64_t cap_bytes,
  * SG_ECAPACITY, need[0] = cells required, need[1] = neighbour pairs
  * required (need may be NULL). */
 sg_status sg_sync(sg_ctx *ctx, int64_t need[2]);
+
+/* Ensembles of independent systems (one bound context each, all SG_FP32C
+ * with grav_variant 2, the same G, eps and stream).  Gravity of all systems
+ * runs as ONE persistent launch: workgroups take (system, 64-target block)
+ * tasks, largest systems first, from a device counter until none is left.
+ * The ensemble keeps pointers into the contexts: do not rebind or destroy
+ * them while it exists.  d_ws: caller-owned device memory of
+ * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task
+ * table is uploaded once, synchronously, by sg_ensemble_create. */
+typedef struct sg_ens sg_ens;   /* opaque */
+size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles);
+sg_status sg_ensemble_create(sg_ctx *const *ctxs, int32_t nsys, void *d_ws, size_t ws_bytes,
+                             sg_ens **out);
+/* Batched gravity (flags SG_GRAV [| SG_POT]) for every system, then each
+ * context's acceleration output is refreshed as in sg_compute_accel. */
+sg_status sg_ensemble_gravity(sg_ens *e, uint32_t flags);
+/* One predictor-corrector step of every system (as sg_step), gravity batched. */
+sg_status sg_ensemble_step(sg_ens *e, double dt, uint32_t flags);
+/* nsteps ensemble steps; with use_graph the steady-state step is captured
+ * once and replayed (as sg_run).  Waits for the stream. */
+sg_status sg_ensemble_run(sg_ens *e, double dt, int64_t nsteps, uint32_t flags, int32_t use_graph);
+const char *sg_ensemble_last_error(const sg_ens *e);
+void sg_ensemble_destroy(sg_ens *e);
 
 /* Stage timing.  When enabled, every kernel group below is bracketed by a
  * pair of HIP events on the context's stream; sg_profile_read() waits for

@@ -4,7 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "sg_internal.h"
@@ -12,6 +14,15 @@
 namespace {
 
 thread_local char g_create_msg[256] = "null context";
+
+// grav_variant 0 (automatic) resolved per precision form: FP64 -> 1 (rsqrt
+// seeded in FP32); FP32C -> 1 (all pairs on the vector ALU).
+constexpr int kAutoVariantFP64 = 1;
+constexpr int kAutoVariantFP32C = 1;
+inline int resolved_variant(const sg_params& p) {
+    if (p.grav_variant != 0) return p.grav_variant;
+    return p.precision == SG_FP32C ? kAutoVariantFP32C : kAutoVariantFP64;
+}
 
 constexpr size_t kAlign = 256;
 inline size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -102,9 +113,9 @@ bool params_ok(const sg_params* p, const char** why) {
     if (p->grav_ipl != 0 && p->grav_ipl != 1 && p->grav_ipl != 2 && p->grav_ipl != 4)
         return *why = "grav_ipl must be 0, 1, 2 or 4", false;
     if (p->grav_split < 0 || p->grav_split > 64) return *why = "grav_split must be in [0, 64]", false;
-    if (p->grav_variant < 0 || p->grav_variant > 1)
-        return *why = "grav_variant must be 0 or 1", false;
-    if (p->precision == SG_FP64 && p->grav_variant == 0 && !(p->eps * p->eps >= 1.2e-38))
+    if (p->grav_variant < 0 || p->grav_variant > 2)
+        return *why = "grav_variant must be 0, 1 or 2", false;
+    if (p->precision == SG_FP64 && p->grav_variant != 2 && !(p->eps * p->eps >= 1.2e-38))
         return *why = "FP32-seeded FP64 gravity needs eps^2 in the FP32 normal range", false;
     for (int r : p->reserved)
         if (r != 0) return *why = "reserved fields must be zero", false;
@@ -247,7 +258,11 @@ void grav_shape(const sg_ctx* c, int* ipl, int* split) {
     int p = c->prm.grav_ipl;
     if (p == 0) p = n >= 4 * 256 * 2048 ? 4 : (n >= 2 * 256 * 1024 ? 2 : 1);
     int s = c->prm.grav_split;
-    const int64_t iblocks = (n + 256 * p - 1) / (256 * p);
+    // targets per workgroup: 256 * ipl (vector-ALU kernels) or 64 (FP32C
+    // with the far field on the matrix cores)
+    const bool mfma = c->prm.precision == SG_FP32C && resolved_variant(c->prm) == 2;
+    const int64_t per = mfma ? 64 : 256 * p;
+    const int64_t iblocks = (n + per - 1) / per;
     if (s == 0) {
         int64_t want = (2048 + iblocks - 1) / iblocks;
         s = (int)(want < 1 ? 1 : (want > 64 ? 64 : want));
@@ -315,8 +330,7 @@ sg_status do_density(sg_ctx* c) {
     return SG_OK;
 }
 
-sg_status do_gravity(sg_ctx* c, bool pot) {
-    sg_grav_args a;
+void grav_args(sg_ctx* c, bool pot, sg_grav_args& a) {
     a.x = c->s.x;
     a.y = c->s.y;
     a.z = c->s.z;
@@ -327,30 +341,39 @@ sg_status do_gravity(sg_ctx* c, bool pot) {
     a.precision = c->prm.precision;
     grav_shape(c, &a.ipl, &a.split);
     a.with_pot = pot ? 1 : 0;
-    a.variant = c->prm.grav_variant;
-    a.order = nullptr;
+    a.variant = resolved_variant(c->prm);
+    a.order = c->prm.precision == SG_FP32C ? c->at<int32_t>(c->L.gorder) : nullptr;
     a.sorted = c->at<void>(c->L.gsorted);
     a.gx = c->at<double>(c->L.gx);
     a.gy = c->at<double>(c->L.gy);
     a.gz = c->at<double>(c->L.gz);
     a.gpot = c->s.pot ? c->s.pot : c->at<double>(c->L.gpot);
     a.part = c->at<double>(c->L.part);
-    if (c->prm.precision == SG_FP32C) {
-        int32_t* order = c->at<int32_t>(c->L.gorder);
-        a.order = order;
-        c->begin(SG_ST_GRAV_PREP);
-        sg_launch_morton_order(c->s.x, c->s.y, c->s.z, c->n, c->grid(), order,
-                               c->at<void>(c->L.morton), c->st);
-        const int rc = sg_launch_grav_sorted(a, c->st);
-        c->end();
-        if (rc != 0) return c->fail(SG_EINVAL, "gravity preparation: missing buffer");
-    }
+}
+
+// FP32C: Morton order, sorted copies and 64-particle boxes at the current
+// positions (nothing to do in the FP64 form).
+sg_status grav_prep(sg_ctx* c, const sg_grav_args& a) {
+    if (c->prm.precision != SG_FP32C) return SG_OK;
+    c->begin(SG_ST_GRAV_PREP);
+    sg_launch_morton_order(c->s.x, c->s.y, c->s.z, c->n, c->grid(), const_cast<int32_t*>(a.order),
+                           c->at<void>(c->L.morton), c->st);
+    const int rc = sg_launch_grav_sorted(a, c->st);
+    c->end();
+    if (rc != 0) return c->fail(SG_EINVAL, "gravity preparation: missing buffer");
+    return SG_OK;
+}
+
+sg_status do_gravity(sg_ctx* c, bool pot) {
+    sg_grav_args a;
+    grav_args(c, pot, a);
+    sg_status r = grav_prep(c, a);
+    if (r != SG_OK) return r;
     c->begin(SG_ST_GRAV);
     const int rc = sg_launch_gravity(a, c->st);
     c->end();
     if (rc != 0) return c->fail(SG_EINVAL, "gravity: missing buffer");
-    sg_status r = c->check_launch("gravity");
-    if (r != SG_OK) return r;
+    if ((r = c->check_launch("gravity")) != SG_OK) return r;
     c->have_grav = true;
     c->have_pot = pot;
     return SG_OK;
@@ -746,6 +769,216 @@ sg_status sg_sync(sg_ctx* c, int64_t need[2]) {
              (long long)g.need_cells, (long long)g.need_nnz);
     return SG_ECAPACITY;
 }
+
+// ------------------------------------------------------------- ensembles --
+
+struct sg_ens {
+    std::vector<sg_ctx*> c;
+    hipStream_t st;
+    sg_ens_sys* d_sys;
+    sg_ens_task* d_tasks;
+    int32_t* d_counter;
+    int32_t ntasks;
+    int nblocks;
+    double eps, G;
+    char msg[256];
+    sg_status fail(sg_status code, const char* m) {
+        snprintf(msg, sizeof(msg), "%s", m);
+        return code;
+    }
+};
+
+namespace {
+
+size_t ens_layout(int32_t nsys, int64_t ntasks, size_t* o_tasks, size_t* o_counter) {
+    size_t o = al(sizeof(sg_ens_sys) * (size_t)nsys);
+    *o_tasks = o;
+    o += al(sizeof(sg_ens_task) * (size_t)(ntasks > 0 ? ntasks : 1));
+    *o_counter = o;
+    o += al(sizeof(int32_t));
+    return o;
+}
+
+sg_status ens_gravity(sg_ens* e, bool pot) {
+    for (sg_ctx* c : e->c) {
+        sg_grav_args a;
+        grav_args(c, pot, a);
+        sg_status r = grav_prep(c, a);
+        if (r != SG_OK) return e->fail(r, c->msg);
+    }
+    sg_ctx* c0 = e->c[0];
+    c0->begin(SG_ST_GRAV);
+    sg_launch_grav_ensemble(e->d_sys, e->d_tasks, e->ntasks, e->d_counter, pot ? 1 : 0, e->eps,
+                            e->G, e->nblocks, e->st);
+    c0->end();
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return e->fail(SG_EDEVICE, hipGetErrorString(err));
+    for (sg_ctx* c : e->c) {
+        c->have_grav = true;
+        c->have_pot = pot;
+    }
+    return SG_OK;
+}
+
+sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
+    if (flags & ~SG_POT) return e->fail(SG_EINVAL, "steps accept only SG_POT");
+    if (!__builtin_isfinite(dt)) return e->fail(SG_EINVAL, "dt must be finite");
+    const bool pot = (flags & SG_POT) != 0;
+    sg_status r;
+    bool need_grav = false;
+    for (sg_ctx* c : e->c) {
+        if (c->predicted) return e->fail(SG_ESTATE, "step inside a predict/correct pair");
+        if (!c->have_nbr && (r = do_build(c)) != SG_OK) return e->fail(r, c->msg);
+        if (!c->have_rho && (r = do_density(c)) != SG_OK) return e->fail(r, c->msg);
+        need_grav |= !c->have_grav || (pot && !c->have_pot);
+    }
+    if (need_grav && (r = ens_gravity(e, pot)) != SG_OK) return r;
+    for (sg_ctx* c : e->c) {
+        if ((r = do_sph(c)) != SG_OK) return e->fail(r, c->msg);
+        do_combine(c);
+        if ((r = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return e->fail(r, c->msg);
+        if ((r = do_build(c)) != SG_OK) return e->fail(r, c->msg);
+        if ((r = do_density(c)) != SG_OK) return e->fail(r, c->msg);
+    }
+    if ((r = ens_gravity(e, pot)) != SG_OK) return r;
+    for (sg_ctx* c : e->c) {
+        if ((r = do_sph(c)) != SG_OK) return e->fail(r, c->msg);
+        do_combine(c);
+        c->accel_after_predict = true;
+        if ((r = do_kick_drift(c, dt, SG_CORRECT)) != SG_OK) return e->fail(r, c->msg);
+    }
+    return SG_OK;
+}
+
+}  // namespace
+
+size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles) {
+    if (nsys < 1 || total_particles < 1) return 0;
+    size_t a, b;
+    return ens_layout(nsys, total_particles / 64 + nsys, &a, &b);
+}
+
+sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size_t ws_bytes,
+                             sg_ens** out) {
+    if (!out || !ctxs || nsys < 1) return SG_EINVAL;
+    *out = nullptr;
+    if (!d_ws || ((uintptr_t)d_ws & (kAlign - 1))) return SG_EINVAL;
+    std::vector<sg_ens_sys> sys((size_t)nsys);
+    std::vector<std::pair<int64_t, sg_ens_task>> tasks;
+    int64_t total = 0;
+    for (int32_t k = 0; k < nsys; ++k) {
+        sg_ctx* c = ctxs[k];
+        if (!c || !c->bound) return SG_EINVAL;
+        if (c->prm.precision != SG_FP32C || resolved_variant(c->prm) != 2) return SG_EINVAL;
+        if (c->st != ctxs[0]->st || c->prm.G != ctxs[0]->prm.G || c->prm.eps != ctxs[0]->prm.eps)
+            return SG_EINVAL;
+        sg_ens_sys& S = sys[(size_t)k];
+        sg_grav_sorted_ptrs(c->at<void>(c->L.gsorted), c->n, &S.xs, &S.ys, &S.zs, &S.ms, &S.sbox);
+        S.order = c->at<int32_t>(c->L.gorder);
+        S.n = c->n;
+        S.gx = c->at<double>(c->L.gx);
+        S.gy = c->at<double>(c->L.gy);
+        S.gz = c->at<double>(c->L.gz);
+        S.gp = c->s.pot ? c->s.pot : c->at<double>(c->L.gpot);
+        const int64_t nb = (c->n + 63) / 64;
+        for (int64_t b = 0; b < nb; ++b) tasks.push_back({c->n, sg_ens_task{k, (int32_t)b}});
+        total += c->n;
+    }
+    // largest systems first (their tasks are the longest)
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [](const std::pair<int64_t, sg_ens_task>& a,
+                        const std::pair<int64_t, sg_ens_task>& b) { return a.first > b.first; });
+    size_t o_tasks, o_counter;
+    const size_t need = ens_layout(nsys, (int64_t)tasks.size(), &o_tasks, &o_counter);
+    if (ws_bytes < need || (int64_t)tasks.size() > total / 64 + nsys) return SG_EINVAL;
+    std::vector<sg_ens_task> tk(tasks.size());
+    for (size_t i = 0; i < tasks.size(); ++i) tk[i] = tasks[i].second;
+    sg_ens* e = new (std::nothrow) sg_ens();
+    if (!e) return SG_EINVAL;
+    e->c.assign(ctxs, ctxs + nsys);
+    e->st = ctxs[0]->st;
+    char* ws = (char*)d_ws;
+    e->d_sys = (sg_ens_sys*)ws;
+    e->d_tasks = (sg_ens_task*)(ws + o_tasks);
+    e->d_counter = (int32_t*)(ws + o_counter);
+    e->ntasks = (int32_t)tk.size();
+    e->eps = ctxs[0]->prm.eps;
+    e->G = ctxs[0]->prm.G;
+    e->msg[0] = 0;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    e->nblocks = 3 * (cus > 0 ? cus : 256);
+    if (e->nblocks > e->ntasks) e->nblocks = e->ntasks;
+    if (hipMemcpyAsync(e->d_sys, sys.data(), sizeof(sg_ens_sys) * sys.size(), hipMemcpyHostToDevice,
+                       e->st) != hipSuccess ||
+        hipMemcpyAsync(e->d_tasks, tk.data(), sizeof(sg_ens_task) * tk.size(),
+                       hipMemcpyHostToDevice, e->st) != hipSuccess ||
+        hipStreamSynchronize(e->st) != hipSuccess) {
+        delete e;
+        return SG_EDEVICE;
+    }
+    *out = e;
+    return SG_OK;
+}
+
+sg_status sg_ensemble_gravity(sg_ens* e, uint32_t flags) {
+    if (!e) return SG_EINVAL;
+    if (flags & ~(SG_GRAV | SG_POT)) return e->fail(SG_EINVAL, "flags: SG_GRAV [| SG_POT]");
+    (void)hipGetLastError();
+    sg_status r = ens_gravity(e, (flags & SG_POT) != 0);
+    if (r != SG_OK) return r;
+    for (sg_ctx* c : e->c) do_combine(c);
+    return SG_OK;
+}
+
+sg_status sg_ensemble_step(sg_ens* e, double dt, uint32_t flags) {
+    if (!e) return SG_EINVAL;
+    (void)hipGetLastError();
+    return ens_step(e, dt, flags);
+}
+
+sg_status sg_ensemble_run(sg_ens* e, double dt, int64_t nsteps, uint32_t flags, int32_t use_graph) {
+    if (!e) return SG_EINVAL;
+    if (nsteps < 0) return e->fail(SG_EINVAL, "nsteps must be >= 0");
+    for (sg_ctx* c : e->c)
+        if (use_graph && c->prof) return e->fail(SG_ESTATE, "stage timing must be off to capture");
+    (void)hipGetLastError();
+    sg_status r;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (use_graph && k == 1) break;
+        if ((r = ens_step(e, dt, flags)) != SG_OK) return r;
+    }
+    if (!use_graph || nsteps < 2)
+        return hipStreamSynchronize(e->st) == hipSuccess ? SG_OK
+                                                          : e->fail(SG_EDEVICE, "stream sync failed");
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(e->st, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return e->fail(SG_EDEVICE, "hipStreamBeginCapture failed");
+    sg_status rc = ens_step(e, dt, flags);
+    hipError_t ec = hipStreamEndCapture(e->st, &graph);
+    if (rc != SG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ec != hipSuccess || !graph) return e->fail(SG_EDEVICE, "hipStreamEndCapture failed");
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return e->fail(SG_EDEVICE, "hipGraphInstantiate failed");
+    }
+    for (int64_t k = 1; k < nsteps && rc == SG_OK; ++k)
+        if (hipGraphLaunch(exec, e->st) != hipSuccess) rc = e->fail(SG_EDEVICE, "hipGraphLaunch failed");
+    if (hipStreamSynchronize(e->st) != hipSuccess && rc == SG_OK)
+        rc = e->fail(SG_EDEVICE, "stream sync failed");
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return rc;
+}
+
+const char* sg_ensemble_last_error(const sg_ens* e) { return e ? e->msg : "null ensemble"; }
+
+void sg_ensemble_destroy(sg_ens* e) { delete e; }
 
 const char* sg_last_error(const sg_ctx* c) { return c ? c->msg : g_create_msg; }
 

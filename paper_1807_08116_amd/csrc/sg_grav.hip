@@ -318,6 +318,287 @@ __global__ __launch_bounds__(kBlock) void k_grav_f32c(
     }
 }
 
+// FP32C form with the far field on the matrix cores.  For a far pair the
+// squared separation expands as r^2 = (|x_i|^2 + eps^2) - 2 x_i . x_j
+// + |x_j|^2, a rank-4 product: one v_mfma_f32_16x16x4f32 gives it for 16
+// targets x 16 sources, with A[i] = (x_i, y_i, z_i, 1), B[j] = (-2x_j,
+// -2y_j, -2z_j, |x_j|^2) and C[i] = |x_i|^2 + eps^2 (offsets from the
+// anchor P, FP32).  The acceleration is accumulated as sum_j s_ij x_j -
+// x_i sum_j s_ij.  Both rewritings lose accuracy only when |x_i|, |x_j| are
+// large against |r_ij|; sources nearer than max(D/8, 4 eps) to the target
+// box are therefore evaluated as in k_grav_f32c's near field (double-float
+// offsets, one target per lane), and for the rest |x| <= 5|r|.  Per
+// workgroup: 4 wavefronts of 16 targets; sources stream through LDS in
+// tiles of kMT.  Lane l of the matrix product holds rows 4(l/16)..+3 and
+// source column l%16.
+constexpr int kMT = 512;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct f32m_lds {
+    float4 hi[2][kMT];
+    float4 lo[2][kMT];
+    float b[2][4][kMT];
+    int near[2][kMT / kSub];
+    double out[kBlock / 64][16][9];
+};
+
+// One workgroup task: targets ib .. ib+63 (sorted order) against sources
+// [j0, j1).  Outputs go to particle order (order[]) at ox[w + t] etc.,
+// w = out_off; raw sums unless final_out.
+template <bool POT>
+__device__ void f32m_task(f32m_lds& L, const double* __restrict__ xs,
+                          const double* __restrict__ ys, const double* __restrict__ zs,
+                          const double* __restrict__ ms, const box6* __restrict__ sbox,
+                          const int32_t* __restrict__ order, int64_t n, int64_t ib, int64_t j0,
+                          int64_t j1, double eps, double G, int final_out,
+                          double* __restrict__ ox, double* __restrict__ oy,
+                          double* __restrict__ oz, double* __restrict__ op, int64_t out_off) {
+    auto& s_hi = L.hi;
+    auto& s_lo = L.lo;
+    auto& s_b = L.b;
+    auto& s_near = L.near;
+    auto& s_out = L.out;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int col = lane & 15, grp = lane >> 4;
+    const box6 bb = sbox[ib / kSub];                           // box of the 64 targets
+    const double Px = 0.5 * (bb.lo[0] + bb.hi[0]);
+    const double Py = 0.5 * (bb.lo[1] + bb.hi[1]);
+    const double Pz = 0.5 * (bb.lo[2] + bb.hi[2]);
+    double diag2 = 0.0;
+    for (int d = 0; d < 3; ++d) diag2 += (bb.hi[d] - bb.lo[d]) * (bb.hi[d] - bb.lo[d]);
+    double near2 = kNearFrac * kNearFrac * diag2;
+    near2 = near2 > 16.0 * eps * eps ? near2 : 16.0 * eps * eps;
+    const float eps2f = (float)(eps * eps);
+
+    // target of this lane for the A operand and the near field: t = col
+    int64_t it = ib + wave * 16 + col;
+    if (it >= n) it = ib;
+    const double tdx = xs[it] - Px, tdy = ys[it] - Py, tdz = zs[it] - Pz;
+    const float hx = (float)tdx, hy = (float)tdy, hz = (float)tdz;
+    const float lx = (float)(tdx - (double)hx), ly = (float)(tdy - (double)hy),
+                lz = (float)(tdz - (double)hz);
+    const float a_op = grp == 0 ? hx : (grp == 1 ? hy : (grp == 2 ? hz : 1.0f));
+    // C operand: rows 4*grp + r of this wave's 16 targets
+    v4f cop;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int64_t ic = ib + wave * 16 + 4 * grp + r;
+        if (ic >= n) ic = ib;
+        const double cx = xs[ic] - Px, cy = ys[ic] - Py, cz = zs[ic] - Pz;
+        cop[r] = (float)(cx * cx + cy * cy + cz * cz + eps * eps);
+    }
+    float fx[4], fy[4], fz[4], f1[4], fp[4];
+    double Fx[4], Fy[4], Fz[4], F1[4], Fp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        fx[r] = fy[r] = fz[r] = f1[r] = fp[r] = 0.0f;
+        Fx[r] = Fy[r] = Fz[r] = F1[r] = Fp[r] = 0.0;
+    }
+    float nx = 0.f, ny = 0.f, nz = 0.f, np = 0.f;
+    double Nx = 0.0, Ny = 0.0, Nz = 0.0, Np = 0.0;
+
+    auto stage = [&](int buf, int64_t jt) {
+#pragma unroll
+        for (int u = 0; u < kMT / kBlock; ++u) {
+            const int jl = u * kBlock + tid;
+            const int64_t j = jt + jl;
+            float4 h = make_float4(0.f, 0.f, 0.f, 0.f), l = make_float4(0.f, 0.f, 0.f, 0.f);
+            float q2 = 0.f;
+            if (j < j1) {
+                const double dx = xs[j] - Px, dy = ys[j] - Py, dz = zs[j] - Pz;
+                h = make_float4((float)dx, (float)dy, (float)dz, (float)ms[j]);
+                l = make_float4((float)(dx - (double)h.x), (float)(dy - (double)h.y),
+                                (float)(dz - (double)h.z), 0.f);
+                q2 = (float)(dx * dx + dy * dy + dz * dz);
+            }
+            s_hi[buf][jl] = h;
+            s_lo[buf][jl] = l;
+            s_b[buf][0][jl] = -2.0f * h.x;
+            s_b[buf][1][jl] = -2.0f * h.y;
+            s_b[buf][2][jl] = -2.0f * h.z;
+            s_b[buf][3][jl] = q2;
+        }
+        if (tid < kMT / kSub) {
+            const int64_t q = jt / kSub + tid;
+            int nr = 0;
+            if (jt + (int64_t)tid * kSub < j1) nr = box_gap2(bb, sbox[q]) < near2;
+            s_near[buf][tid] = nr;
+        }
+    };
+
+    stage(0, j0);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t jt = j0; jt < j1; jt += kMT) {
+        const bool more = jt + kMT < j1;
+        for (int sb = 0; sb < kMT / kSub; ++sb) {
+            if (s_near[cur][sb]) {
+                // near field: target col, sources sb*64 + 4k + grp
+#pragma unroll 4
+                for (int k = 0; k < kSub / 4; ++k) {
+                    const int jl = sb * kSub + 4 * k + grp;
+                    const float4 q = s_hi[cur][jl];
+                    const float4 ql = s_lo[cur][jl];
+                    const float dx = (q.x - hx) + (ql.x - lx);
+                    const float dy = (q.y - hy) + (ql.y - ly);
+                    const float dz = (q.z - hz) + (ql.z - lz);
+                    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+                    const float rinv = __builtin_amdgcn_rsqf(r2);
+                    const float mr = q.w * rinv;
+                    const float sv = mr * (rinv * rinv);
+                    nx = __builtin_fmaf(sv, dx, nx);
+                    ny = __builtin_fmaf(sv, dy, ny);
+                    nz = __builtin_fmaf(sv, dz, nz);
+                    if (POT) np += mr;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < kSub / 16; ++c) {
+                    const int jl = sb * kSub + c * 16 + col;
+                    const float b = s_b[cur][grp][sb * kSub + c * 16 + col];
+                    const v4f d = __builtin_amdgcn_mfma_f32_16x16x4f32(a_op, b, cop, 0, 0, 0);
+                    const float4 q = s_hi[cur][jl];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float rinv = __builtin_amdgcn_rsqf(d[r]);
+                        const float mr = q.w * rinv;
+                        const float sv = mr * (rinv * rinv);
+                        fx[r] = __builtin_fmaf(sv, q.x, fx[r]);
+                        fy[r] = __builtin_fmaf(sv, q.y, fy[r]);
+                        fz[r] = __builtin_fmaf(sv, q.z, fz[r]);
+                        f1[r] += sv;
+                        if (POT) fp[r] += mr;
+                    }
+                }
+            }
+        }
+        // fold this tile's FP32 partial sums into FP64
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Fx[r] += (double)fx[r];
+            Fy[r] += (double)fy[r];
+            Fz[r] += (double)fz[r];
+            F1[r] += (double)f1[r];
+            if (POT) Fp[r] += (double)fp[r];
+            fx[r] = fy[r] = fz[r] = f1[r] = fp[r] = 0.0f;
+        }
+        Nx += (double)nx;
+        Ny += (double)ny;
+        Nz += (double)nz;
+        if (POT) Np += (double)np;
+        nx = ny = nz = np = 0.0f;
+        __syncthreads();
+        if (more) stage(cur ^ 1, jt + kMT);
+        __syncthreads();
+        cur ^= 1;
+    }
+    // far sums: reduce over the 16 source columns of each row group
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        for (int o = 1; o < 16; o <<= 1) {
+            Fx[r] += __shfl_xor(Fx[r], o, 64);
+            Fy[r] += __shfl_xor(Fy[r], o, 64);
+            Fz[r] += __shfl_xor(Fz[r], o, 64);
+            F1[r] += __shfl_xor(F1[r], o, 64);
+            if (POT) Fp[r] += __shfl_xor(Fp[r], o, 64);
+        }
+    }
+    // near sums: reduce over the 4 source quarters of each target
+    for (int o = 16; o < 64; o <<= 1) {
+        Nx += __shfl_xor(Nx, o, 64);
+        Ny += __shfl_xor(Ny, o, 64);
+        Nz += __shfl_xor(Nz, o, 64);
+        if (POT) Np += __shfl_xor(Np, o, 64);
+    }
+    if (col == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double* o = s_out[wave][4 * grp + r];
+            o[0] = Fx[r];
+            o[1] = Fy[r];
+            o[2] = Fz[r];
+            o[3] = F1[r];
+            o[4] = Fp[r];
+        }
+    }
+    if (grp == 0) {
+        double* o = s_out[wave][col];
+        o[5] = Nx;
+        o[6] = Ny;
+        o[7] = Nz;
+        o[8] = Np;
+    }
+    __syncthreads();
+    if (grp == 0) {
+        const int64_t i = ib + wave * 16 + col;
+        if (i < n) {
+            int32_t t = order[i];
+            if ((uint64_t)t < (uint64_t)n) {
+                const double* o = s_out[wave][col];
+                const double gx = o[0] - (double)hx * o[3] + o[5];
+                const double gy = o[1] - (double)hy * o[3] + o[6];
+                const double gz = o[2] - (double)hz * o[3] + o[7];
+                const double pp = o[4] + o[8];
+                if (final_out) {
+                    ox[t] = G * gx;
+                    oy[t] = G * gy;
+                    oz[t] = G * gz;
+                    if (POT) op[t] = -G * (pp - ms[i] / eps);
+                } else {
+                    const int64_t w = out_off + t;
+                    ox[w] = gx;
+                    oy[w] = gy;
+                    oz[w] = gz;
+                    if (POT) op[w] = pp;
+                }
+            }
+        }
+    }
+    __syncthreads();                             // LDS free for the next task
+}
+
+template <bool POT>
+__global__ __launch_bounds__(kBlock) void k_grav_f32m(
+    const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ zs,
+    const double* __restrict__ ms, const box6* __restrict__ sbox, const int32_t* __restrict__ order,
+    int64_t n, int64_t jchunk, double eps, double G, int final_out, double* __restrict__ ox,
+    double* __restrict__ oy, double* __restrict__ oz, double* __restrict__ op, int64_t ostride) {
+    __shared__ f32m_lds L;
+    const int64_t j0 = (int64_t)blockIdx.y * jchunk;
+    int64_t j1 = j0 + jchunk;
+    if (j1 > n) j1 = n;
+    f32m_task<POT>(L, xs, ys, zs, ms, sbox, order, n, (int64_t)blockIdx.x * 64, j0, j1, eps, G,
+                   final_out, ox, oy, oz, op, (int64_t)blockIdx.y * ostride);
+}
+
+// Persistent launch over the target blocks of several independent systems:
+// each workgroup takes the next (system, block) task from a counter until
+// none is left; tasks are listed largest system first.
+template <bool POT>
+__global__ __launch_bounds__(kBlock) void k_grav_f32m_ens(const sg_ens_sys* __restrict__ sys,
+                                                          const sg_ens_task* __restrict__ tasks,
+                                                          int32_t ntasks, int32_t* counter,
+                                                          double eps, double G) {
+    __shared__ f32m_lds L;
+    __shared__ int32_t s_task;
+    for (;;) {
+        if (threadIdx.x == 0) s_task = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t t = s_task;
+        __syncthreads();
+        if (t >= ntasks) break;                  // uniform: every wavefront leaves here
+        const sg_ens_task tk = tasks[t];
+        const sg_ens_sys S = sys[tk.sys];
+        f32m_task<POT>(L, S.xs, S.ys, S.zs, S.ms, (const box6*)S.sbox, S.order, S.n,
+                       (int64_t)tk.blk * 64, 0, S.n, eps, G, 1, S.gx, S.gy, S.gz, S.gp, 0);
+    }
+}
+
+__global__ void k_counter_reset(int32_t* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
 // Gather positions and masses into Morton order and build the bounding box
 // of every run of kSub sorted particles (one wavefront per run).
 __global__ __launch_bounds__(kBlock) void k_sorted_boxes(
@@ -387,7 +668,7 @@ void launch_t(const sg_grav_args& a, dim3 grid, int64_t jchunk, int final_out, d
                            a.ms, (const box6*)a.sbox, a.order, a.n, jchunk,
                            (float)(a.eps * a.eps), a.G, inv_eps, final_out, ox, oy, oz, op,
                            ostride);
-    else if (a.variant == 1)
+    else if (a.variant == 2)
         hipLaunchKernelGGL((k_grav_f64<IPL, POT, false>), grid, dim3(kBlock), 0, st, a.x, a.y, a.z,
                            a.m, a.n, jchunk, a.eps * a.eps, a.G, inv_eps, final_out, ox, oy, oz,
                            op, ostride);
@@ -425,6 +706,31 @@ void sorted_views(sg_grav_args& a) {
 }
 }  // namespace
 
+void sg_grav_sorted_ptrs(void* sorted, int64_t n, const double** xs, const double** ys,
+                         const double** zs, const double** ms, const void** sbox) {
+    sg_grav_args a;
+    a.sorted = sorted;
+    a.n = n;
+    sorted_views(a);
+    *xs = a.xs;
+    *ys = a.ys;
+    *zs = a.zs;
+    *ms = a.ms;
+    *sbox = a.sbox;
+}
+
+void sg_launch_grav_ensemble(const sg_ens_sys* d_sys, const sg_ens_task* d_tasks, int32_t ntasks,
+                             int32_t* d_counter, int with_pot, double eps, double G, int nblocks,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, d_counter);
+    if (with_pot)
+        hipLaunchKernelGGL((k_grav_f32m_ens<true>), dim3(nblocks), dim3(kBlock), 0, st, d_sys,
+                           d_tasks, ntasks, d_counter, eps, G);
+    else
+        hipLaunchKernelGGL((k_grav_f32m_ens<false>), dim3(nblocks), dim3(kBlock), 0, st, d_sys,
+                           d_tasks, ntasks, d_counter, eps, G);
+}
+
 int sg_launch_grav_sorted(const sg_grav_args& a_in, hipStream_t st) {
     if (!a_in.order || !a_in.sorted || !a_in.x || !a_in.y || !a_in.z || !a_in.m || a_in.n < 1)
         return -1;
@@ -444,13 +750,15 @@ int sg_launch_gravity(const sg_grav_args& a_in, hipStream_t st) {
     if (a_in.precision == SG_FP32C && (!a_in.order || !a_in.sorted)) return -1;
     sg_grav_args a = a_in;
     if (a.precision == SG_FP32C) sorted_views(a);
+    const bool mfma = a.precision == SG_FP32C && a.variant == 2;
     const int ipl = a.ipl;
-    const int64_t per = (int64_t)kBlock * ipl;
+    const int64_t per = mfma ? 64 : (int64_t)kBlock * ipl;
     const int64_t iblocks = (a.n + per - 1) / per;
     int split = a.split < 1 ? 1 : a.split;
     // source chunk: a multiple of the tile, covering n in `split` pieces
+    const int64_t tile = mfma ? kMT : kTile;
     int64_t jchunk = (a.n + split - 1) / split;
-    jchunk = (jchunk + kTile - 1) / kTile * kTile;
+    jchunk = (jchunk + tile - 1) / tile * tile;
     split = (int)((a.n + jchunk - 1) / jchunk);
     const dim3 grid((unsigned)iblocks, (unsigned)split);
     const int final_out = split == 1;
@@ -463,7 +771,16 @@ int sg_launch_gravity(const sg_grav_args& a_in, hipStream_t st) {
         oz = a.part + 2 * comp;
         op = a.part + 3 * comp;
     }
-    switch (ipl) {
+    if (mfma) {
+        if (a.with_pot)
+            hipLaunchKernelGGL((k_grav_f32m<true>), grid, dim3(kBlock), 0, st, a.xs, a.ys, a.zs, a.ms,
+                               (const box6*)a.sbox, a.order, a.n, jchunk, a.eps, a.G, final_out,
+                               ox, oy, oz, op, ostride);
+        else
+            hipLaunchKernelGGL((k_grav_f32m<false>), grid, dim3(kBlock), 0, st, a.xs, a.ys, a.zs,
+                               a.ms, (const box6*)a.sbox, a.order, a.n, jchunk, a.eps, a.G,
+                               final_out, ox, oy, oz, op, ostride);
+    } else switch (ipl) {
         case 1: launch_ipl<1>(a, grid, jchunk, final_out, ox, oy, oz, op, ostride, st); break;
         case 2: launch_ipl<2>(a, grid, jchunk, final_out, ox, oy, oz, op, ostride, st); break;
         default: launch_ipl<4>(a, grid, jchunk, final_out, ox, oy, oz, op, ostride, st); break;

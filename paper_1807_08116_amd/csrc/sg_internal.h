@@ -128,7 +128,8 @@ struct sg_grav_args {
     int64_t n;
     double G, eps;
     int precision, ipl, split, with_pot;
-    int variant;                        // FP64: 0 = FP32-seeded rsqrt, 1 = FP64-seeded
+    int variant;                        // resolved: FP64 1 = FP32-seeded rsqrt, 2 = FP64-seeded;
+                                        // FP32C 1 = vector ALU, 2 = matrix-core far field
     const int32_t* order;               // FP32C: Morton order of the particles, else null
     void* sorted;                       // FP32C: scratch of sg_grav_sorted_bytes(n)
     const double *xs, *ys, *zs, *ms;    // (set by the launcher) sorted copies
@@ -142,6 +143,24 @@ size_t sg_grav_sorted_bytes(int64_t n);
 // Both return -1 (and launch nothing) when a required pointer is missing.
 int sg_launch_grav_sorted(const sg_grav_args& a, hipStream_t st);
 int sg_launch_gravity(const sg_grav_args& a, hipStream_t st);
+
+// Ensembles: one persistent launch over (system, 64-target block) tasks of
+// several systems in the FP32C form with the matrix-core far field.
+struct sg_ens_sys {
+    const double *xs, *ys, *zs, *ms;    // Morton-sorted copies
+    const void* sbox;                   // 64-particle boxes
+    const int32_t* order;
+    int64_t n;
+    double *gx, *gy, *gz, *gp;          // outputs, particle order
+};
+struct sg_ens_task {
+    int32_t sys, blk;
+};
+void sg_grav_sorted_ptrs(void* sorted, int64_t n, const double** xs, const double** ys,
+                         const double** zs, const double** ms, const void** sbox);
+void sg_launch_grav_ensemble(const sg_ens_sys* d_sys, const sg_ens_task* d_tasks, int32_t ntasks,
+                             int32_t* d_counter, int with_pot, double eps, double G, int nblocks,
+                             hipStream_t st);
 
 // Spatial (Morton) order of all N particles for the FP32C gravity targets.
 size_t sg_morton_tmp_bytes(int64_t n);

@@ -160,3 +160,21 @@ def make(name, seed=None, scale=1.0):
         return isolated(max(1, int(cfg["n_gas"] * scale)), max(1, int(cfg["n_halo"] * scale)), seed)
     return collision(max(1, int(cfg["n_gas_per"] * scale)), max(1, int(cfg["n_halo_per"] * scale)),
                      seed, b=cfg["b"], v=cfg["v"], mass_ratio=cfg.get("mass_ratio", 1.0))
+
+
+def ensemble(nsys=64, seed=SEED_BASE + 4, n_min=8192, n_max=262144, scale=1.0):
+    """Independent two-system collisions: N per system log-uniform in
+    [n_min, n_max] (a multiple of 4, gas:halo 1:1, two galaxies each), impact
+    parameter U[0, 3], closing speed U[0.5, 2].  Returns a list of states."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(nsys):
+        n = int(np.exp(rng.uniform(np.log(n_min), np.log(n_max))) * scale)
+        n = max(8, n - n % 4)
+        b = rng.uniform(0.0, 3.0)
+        v = rng.uniform(0.5, 2.0)
+        sub = int(rng.integers(0, 2 ** 31))
+        st = collision(n // 4, n // 4, sub, b=b, v=v)
+        st["meta"] = {"n": n, "b": b, "v": v, "seed": sub}
+        out.append(st)
+    return out

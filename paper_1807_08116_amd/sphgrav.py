@@ -33,6 +33,8 @@ STATUS_NAMES = {0: "SG_OK", 1: "SG_EINVAL", 2: "SG_ECAPACITY", 3: "SG_EDEVICE", 
 EXPORTED = ["sg_workspace_bytes", "sg_create", "sg_bind_state", "sg_build_neighbors",
             "sg_compute_density", "sg_compute_accel", "sg_kick_drift", "sg_step", "sg_run", "sg_cfl_dt", "sg_update_h",
             "sg_diagnostics", "sg_export", "sg_sync", "sg_profile_enable", "sg_profile_read",
+            "sg_ensemble_bytes", "sg_ensemble_create", "sg_ensemble_gravity", "sg_ensemble_step",
+            "sg_ensemble_run", "sg_ensemble_last_error", "sg_ensemble_destroy",
             "sg_last_error", "sg_destroy", "sg_version"]
 STAGES = ["sort", "nbr", "density", "sph", "grav_prep", "grav", "update", "diag"]
 
@@ -119,6 +121,20 @@ def lib():
     L.sg_profile_enable.argtypes = [vp, i32]
     L.sg_profile_read.restype = C.c_int
     L.sg_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.sg_ensemble_bytes.restype = C.c_size_t
+    L.sg_ensemble_bytes.argtypes = [i32, i64]
+    L.sg_ensemble_create.restype = C.c_int
+    L.sg_ensemble_create.argtypes = [C.POINTER(vp), i32, vp, C.c_size_t, C.POINTER(vp)]
+    L.sg_ensemble_gravity.restype = C.c_int
+    L.sg_ensemble_gravity.argtypes = [vp, u32]
+    L.sg_ensemble_step.restype = C.c_int
+    L.sg_ensemble_step.argtypes = [vp, dbl, u32]
+    L.sg_ensemble_run.restype = C.c_int
+    L.sg_ensemble_run.argtypes = [vp, dbl, i64, u32, i32]
+    L.sg_ensemble_last_error.restype = C.c_char_p
+    L.sg_ensemble_last_error.argtypes = [vp]
+    L.sg_ensemble_destroy.restype = None
+    L.sg_ensemble_destroy.argtypes = [vp]
     L.sg_last_error.restype = C.c_char_p
     L.sg_last_error.argtypes = [vp]
     L.sg_destroy.restype = None
@@ -378,3 +394,53 @@ class Engine:
     def numpy(self, name):
         self.ctx.torch.cuda.synchronize()
         return self.dev[name].cpu().numpy()
+
+
+class Ensemble:
+    """Independent systems (one Engine each, FP32C, one shared stream) whose
+    gravity runs as one persistent launch."""
+
+    def __init__(self, states, device="cuda", **kw):
+        import torch
+        self.torch = torch
+        self.stream = torch.cuda.Stream(device=torch.device(device))
+        kw.setdefault("grav_variant", 2)
+        self.engines = [Engine(st, precision=SG_FP32C, device=device, stream=self.stream, **kw)
+                        for st in states]
+        total = sum(e.n for e in self.engines)
+        L = lib()
+        nbytes = L.sg_ensemble_bytes(len(self.engines), total)
+        self.ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))
+        ptr = (self.ws_raw.data_ptr() + 255) & ~255
+        handles = (C.c_void_p * len(self.engines))(*[e.ctx.h.value for e in self.engines])
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        rc = L.sg_ensemble_create(handles, len(self.engines), C.c_void_p(ptr), nbytes, C.byref(h))
+        if rc != SG_OK:
+            raise SGError(rc, "sg_ensemble_create failed")
+        self.h = h
+
+    def _check(self, rc, what):
+        if rc != SG_OK:
+            raise SGError(rc, "%s: %s" % (what, lib().sg_ensemble_last_error(self.h).decode()))
+
+    def gravity(self, flags=SG_GRAV | SG_POT):
+        self._check(lib().sg_ensemble_gravity(self.h, flags), "sg_ensemble_gravity")
+
+    def step(self, dt, flags=0):
+        self._check(lib().sg_ensemble_step(self.h, float(dt), flags), "sg_ensemble_step")
+
+    def run(self, dt, nsteps, flags=0, use_graph=True):
+        self._check(lib().sg_ensemble_run(self.h, float(dt), int(nsteps), flags,
+                                          1 if use_graph else 0), "sg_ensemble_run")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().sg_ensemble_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

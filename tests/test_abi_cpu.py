@@ -39,7 +39,7 @@ def test_workspace_validation(sg):
     assert sg.workspace_bytes(good, caps) > 0
     for bad in (dict(eps=0.0), dict(eps=-1.0), dict(gamma=1.0), dict(alpha=-1.0),
                 dict(eta=0.0), dict(precision=7), dict(grav_ipl=3), dict(grav_split=65),
-                dict(G=float("nan")), dict(grav_variant=2), dict(eps=1e-20)):
+                dict(G=float("nan")), dict(grav_variant=3), dict(eps=1e-20)):
         assert sg.workspace_bytes(sg.make_params(**bad), caps) == 0, bad
     p = sg.make_params()
     p.reserved[2] = 1

@@ -120,8 +120,8 @@ def test_c0_forces(sg, orc, c0, c0_ref, precision):
     assert e_pot < tol
 
 
-@pytest.mark.parametrize("ipl,split,variant", [(1, 1, 0), (2, 3, 1), (4, 1, 0), (4, 1, 1),
-                                               (1, 64, 0), (4, 7, 1)])
+@pytest.mark.parametrize("ipl,split,variant", [(1, 1, 0), (2, 3, 1), (4, 1, 2), (4, 1, 1),
+                                               (1, 64, 2), (4, 7, 1), (0, 0, 2), (0, 5, 2)])
 def test_gravity_launch_shapes(sg, orc, c0, c0_ref, ipl, split, variant):
     ref, *_ = c0_ref
     for p in (sg.SG_FP64, sg.SG_FP32C):
