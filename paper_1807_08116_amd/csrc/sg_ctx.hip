@@ -38,8 +38,7 @@ struct layout {
     size_t key, perm, tmp;
     size_t count, cursor, hmax, off;
     size_t scan;
-    size_t xs, ys, zs, hs, ms, vxs, vys, vzs, es, rho_s, P_s, c_s;
-    size_t hs_f, ms_f, vx_f, vy_f, vz_f, rho_f, P_f, c_f;
+    size_t xs, ys, zs, hs, ms, rho_s, prec, f64, f32;
     size_t ncnt, nbr_off, nbr_idx;
     size_t asx, asy, asz;
     size_t gx, gy, gz, gpot;
@@ -70,11 +69,11 @@ layout make_layout(const sg_params* p, const sg_caps* c) {
     L.hmax = take(8 * C);
     L.off = take(8 * (C + 1));
     L.scan = take(sg_scan_tmp_bytes(C > ng + 1 ? C : ng + 1));
-    size_t* f64s[] = {&L.xs, &L.ys, &L.zs, &L.hs, &L.ms, &L.vxs, &L.vys,
-                      &L.vzs, &L.es, &L.rho_s, &L.P_s, &L.c_s};
+    size_t* f64s[] = {&L.xs, &L.ys, &L.zs, &L.hs, &L.ms, &L.rho_s};
     for (size_t* q : f64s) *q = take(8 * ng);
-    size_t* f32s[] = {&L.hs_f, &L.ms_f, &L.vx_f, &L.vy_f, &L.vz_f, &L.rho_f, &L.P_f, &L.c_f};
-    for (size_t* q : f32s) *q = take(f32 ? 4 * ng : 0);
+    L.prec = take(sizeof(sg_prec) * ng);
+    L.f64 = take(sizeof(sg_frec64) * ng);          // also used by the time-step rule
+    L.f32 = take(f32 ? sizeof(sg_frec32) * ng : 0);
     L.ncnt = take(4 * ng);
     L.nbr_off = take(8 * (ng + 1));
     L.nbr_idx = take(4 * Z);
@@ -214,21 +213,10 @@ struct sg_ctx {
         b.zs = at<double>(L.zs);
         b.hs = at<double>(L.hs);
         b.ms = at<double>(L.ms);
-        b.vxs = at<double>(L.vxs);
-        b.vys = at<double>(L.vys);
-        b.vzs = at<double>(L.vzs);
-        b.es = at<double>(L.es);
         b.rho_s = at<double>(L.rho_s);
-        b.P_s = at<double>(L.P_s);
-        b.c_s = at<double>(L.c_s);
-        b.hs_f = at<float>(L.hs_f);
-        b.ms_f = at<float>(L.ms_f);
-        b.vx_f = at<float>(L.vx_f);
-        b.vy_f = at<float>(L.vy_f);
-        b.vz_f = at<float>(L.vz_f);
-        b.rho_f = at<float>(L.rho_f);
-        b.P_f = at<float>(L.P_f);
-        b.c_f = at<float>(L.c_f);
+        b.prec = at<sg_prec>(L.prec);
+        b.f64 = at<sg_frec64>(L.f64);
+        b.f32 = at<sg_frec32>(L.f32);
         b.perm = at<int32_t>(L.perm);
         b.nbr_off = at<int64_t>(L.nbr_off);
         b.nbr_idx = at<int32_t>(L.nbr_idx);
@@ -299,7 +287,8 @@ sg_status do_build(sg_ctx* c) {
     sg_launch_scan(count, off, 0, &g->M, C, scan, st);
     sg_launch_scatter_rank(key, ng, g, off, cursor, c->at<int32_t>(c->L.tmp),
                            c->at<int32_t>(c->L.perm), st);
-    sg_launch_gather_gas(b.perm, ng, g, s.x, s.y, s.z, s.h, s.m, b.xs, b.ys, b.zs, b.hs, b.ms, st);
+    sg_launch_gather_gas(b.perm, ng, g, s.x, s.y, s.z, s.h, s.m, b.xs, b.ys, b.zs, b.hs, b.ms,
+                         b.prec, st);
     c->end();
     c->begin(SG_ST_NBR);
     int32_t* ncnt = c->at<int32_t>(c->L.ncnt);

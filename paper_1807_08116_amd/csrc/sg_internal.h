@@ -77,10 +77,11 @@ void sg_launch_keys_count(const double* x, const double* y, const double* z, con
 void sg_launch_scatter_rank(const int32_t* key, int64_t ng, const sg_grid_dev* g,
                             const int64_t* off, int32_t* cursor, int32_t* tmp, int32_t* perm,
                             hipStream_t st);
+struct sg_prec;
 void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
                           const double* x, const double* y, const double* z, const double* h,
                           const double* m, double* xs, double* ys, double* zs, double* hs,
-                          double* ms, hipStream_t st);
+                          double* ms, sg_prec* prec, hipStream_t st);
 
 // Neighbour lists.
 void sg_launch_nbr_count(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
@@ -93,14 +94,24 @@ void sg_launch_nbr_fill(const sg_grid_dev* g, int64_t ng, const double* xs, cons
                         const int64_t* nbr_off, int32_t* nbr_idx, int64_t nnz_cap,
                         hipStream_t st);
 
-// SPH.
+// SPH.  Per-particle data in sorted-slot order is packed into one record
+// per particle, so a neighbour gather touches one or two cache lines.
+struct alignas(64) sg_prec {          // positions for the density pass
+    double x, y, z, h, m, pad[3];
+};
+struct alignas(32) sg_frec64 {        // FP64 force pass
+    double x, y, z, h, m, vx, vy, vz, rho, P, c, pad;   // P = p / rho^2
+};
+struct alignas(64) sg_frec32 {        // FP32C force pass (FP64 positions)
+    double x, y, z;
+    float h, m, vx, vy, vz, rho, P, c, pad[2];
+};
 struct sg_sph_bufs {
-    // sorted gas state (FP64)
-    double *xs, *ys, *zs, *hs, *ms;
-    double *vxs, *vys, *vzs, *es;
-    double *rho_s, *P_s, *c_s;          // rho, p/rho^2, sound speed
-    // FP32 mirrors used by the FP32C form
-    float *hs_f, *ms_f, *vx_f, *vy_f, *vz_f, *rho_f, *P_f, *c_f;
+    double *xs, *ys, *zs, *hs, *ms;     // sorted SoA (neighbour search, h update)
+    double* rho_s;                      // density by slot
+    sg_prec* prec;
+    sg_frec64* f64;
+    sg_frec32* f32;
     const int32_t* perm;
     const int64_t* nbr_off;
     const int32_t* nbr_idx;

@@ -427,16 +427,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_gas(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const double* __restrict__ h, const double* __restrict__ m, double* __restrict__ xs,
     double* __restrict__ ys, double* __restrict__ zs, double* __restrict__ hs,
-    double* __restrict__ ms) {
+    double* __restrict__ ms, sg_prec* __restrict__ prec) {
     if (g->err & SGE_SORT_FATAL) return;
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= ng) return;
     const int32_t i = perm[s];
-    xs[s] = x[i];
-    ys[s] = y[i];
-    zs[s] = z[i];
-    hs[s] = h[i];
-    ms[s] = m[i];
+    const double px = x[i], py = y[i], pz = z[i], ph = h[i], pm = m[i];
+    xs[s] = px;
+    ys[s] = py;
+    zs[s] = pz;
+    hs[s] = ph;
+    ms[s] = pm;
+    prec[s] = sg_prec{px, py, pz, ph, pm, {0.0, 0.0, 0.0}};
 }
 
 // ------------------------------------------------------ Morton ordering --
@@ -647,9 +649,9 @@ void sg_launch_scatter_rank(const int32_t* key, int64_t ng, const sg_grid_dev* g
 void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
                           const double* x, const double* y, const double* z, const double* h,
                           const double* m, double* xs, double* ys, double* zs, double* hs,
-                          double* ms, hipStream_t st) {
+                          double* ms, sg_prec* prec, hipStream_t st) {
     hipLaunchKernelGGL(k_gather_gas, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, st, perm, ng,
-                       g, x, y, z, h, m, xs, ys, zs, hs, ms);
+                       g, x, y, z, h, m, xs, ys, zs, hs, ms, prec);
 }
 
 // Workspace of the Morton order: two key/value buffers, the digit histogram

@@ -48,16 +48,16 @@ __global__ __launch_bounds__(kBlock) void k_density_f64(sg_sph_bufs b, const sg_
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= ng) return;
-    const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s], hi = b.hs[s];
-    double acc = b.ms[s] / (kPi * hi * hi * hi);      // self term m_i W(0, h_i)
+    const sg_prec pi = b.prec[s];
+    double acc = pi.m / (kPi * pi.h * pi.h * pi.h);      // self term m_i W(0, h_i)
     const int64_t e1 = b.nbr_off[s + 1];
     for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
-        const int32_t t = b.nbr_idx[e];
-        const double dx = xi - b.xs[t], dy = yi - b.ys[t], dz = zi - b.zs[t];
+        const sg_prec pj = b.prec[b.nbr_idx[e]];
+        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        const double hij = 0.5 * (hi + b.hs[t]);
+        const double hij = 0.5 * (pi.h + pj.h);
         const double inv = 1.0 / hij;
-        acc += b.ms[t] * spline_shape(r * inv) * (inv * inv * inv) * (1.0 / kPi);
+        acc += pj.m * spline_shape(r * inv) * (inv * inv * inv) * (1.0 / kPi);
     }
     b.rho_s[s] = acc;
     rho_out[b.perm[s]] = acc;
@@ -68,28 +68,26 @@ __global__ __launch_bounds__(kBlock) void k_density_f32(sg_sph_bufs b, const sg_
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= ng) return;
-    const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s];
-    const float hi = (float)b.hs[s];
-    b.hs_f[s] = hi;
-    b.ms_f[s] = (float)b.ms[s];
-    kahan acc{(float)(b.ms[s] / (kPi * b.hs[s] * b.hs[s] * b.hs[s])), 0.0f};
+    const sg_prec pi = b.prec[s];
+    const float hi = (float)pi.h;
+    kahan acc{(float)(pi.m / (kPi * pi.h * pi.h * pi.h)), 0.0f};
     const int64_t e1 = b.nbr_off[s + 1];
     for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
-        const int32_t t = b.nbr_idx[e];
-        const float dx = (float)(xi - b.xs[t]), dy = (float)(yi - b.ys[t]),
-                    dz = (float)(zi - b.zs[t]);
+        const sg_prec pj = b.prec[b.nbr_idx[e]];
+        const float dx = (float)(pi.x - pj.x), dy = (float)(pi.y - pj.y), dz = (float)(pi.z - pj.z);
         const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-        const float hij = 0.5f * (hi + (float)b.hs[t]);
+        const float hij = 0.5f * (hi + (float)pj.h);
         const float inv = 1.0f / hij;
-        acc.add((float)b.ms[t] * spline_shape(r * inv) * (inv * inv * inv) * (float)(1.0 / kPi));
+        acc.add((float)pj.m * spline_shape(r * inv) * (inv * inv * inv) * (float)(1.0 / kPi));
     }
     const double rho = acc.value();
     b.rho_s[s] = rho;
     rho_out[b.perm[s]] = rho;
 }
 
-// Gather the velocities and energies the force pass should use into slot
-// order and evaluate p / rho^2 and the sound speed sqrt(gamma p / rho).
+// Pack the state the force pass should use (velocities and energies of the
+// current or predicted state) into one record per slot, with p / rho^2 and
+// the sound speed sqrt(gamma p / rho) from the ideal-gas law.
 __global__ __launch_bounds__(kBlock) void k_sph_prep(sg_sph_bufs b, const sg_grid_dev* g,
                                                      int64_t ng, int precision, double gamma,
                                                      const double* __restrict__ vx,
@@ -100,23 +98,28 @@ __global__ __launch_bounds__(kBlock) void k_sph_prep(sg_sph_bufs b, const sg_gri
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= ng) return;
     const int32_t i = b.perm[s];
+    const sg_prec q = b.prec[s];
     const double rho = b.rho_s[s];
     const double p = (gamma - 1.0) * rho * e[i];
     const double P = p / (rho * rho);
     const double c = sqrt(gamma * p / rho);
     if (precision == SG_FP32C) {
-        b.vx_f[s] = (float)vx[i];
-        b.vy_f[s] = (float)vy[i];
-        b.vz_f[s] = (float)vz[i];
-        b.rho_f[s] = (float)rho;
-        b.P_f[s] = (float)P;
-        b.c_f[s] = (float)c;
+        sg_frec32 r;
+        r.x = q.x;
+        r.y = q.y;
+        r.z = q.z;
+        r.h = (float)q.h;
+        r.m = (float)q.m;
+        r.vx = (float)vx[i];
+        r.vy = (float)vy[i];
+        r.vz = (float)vz[i];
+        r.rho = (float)rho;
+        r.P = (float)P;
+        r.c = (float)c;
+        r.pad[0] = r.pad[1] = 0.0f;
+        b.f32[s] = r;
     } else {
-        b.vxs[s] = vx[i];
-        b.vys[s] = vy[i];
-        b.vzs[s] = vz[i];
-        b.P_s[s] = P;
-        b.c_s[s] = c;
+        b.f64[s] = sg_frec64{q.x, q.y, q.z, q.h, q.m, vx[i], vy[i], vz[i], rho, P, c, 0.0};
     }
 }
 
@@ -129,34 +132,32 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f64(sg_sph_bufs b, const s
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= ng) return;
-    const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s], hi = b.hs[s];
-    const double vxi = b.vxs[s], vyi = b.vys[s], vzi = b.vzs[s];
-    const double Pi_ = b.P_s[s], ci = b.c_s[s], rhoi = b.rho_s[s];
+    const sg_frec64 a = b.f64[s];
     const double kgrad = -45.0 / (64.0 * kPi);
     double sx = 0, sy = 0, sz = 0, se = 0;
     const int64_t e1 = b.nbr_off[s + 1];
     for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
-        const int32_t t = b.nbr_idx[e];
-        const double dx = xi - b.xs[t], dy = yi - b.ys[t], dz = zi - b.zs[t];
+        const sg_frec64 o = b.f64[b.nbr_idx[e]];
+        const double dx = a.x - o.x, dy = a.y - o.y, dz = a.z - o.z;
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 == 0.0) continue;                       // coincident pair: no gradient
         const double r = sqrt(r2);
-        const double hij = 0.5 * (hi + b.hs[t]);
+        const double hij = 0.5 * (a.h + o.h);
         const double inv = 1.0 / hij;
         const double q = 2.0 - r * inv;
         if (q <= 0.0) continue;
-        const double dvx = vxi - b.vxs[t], dvy = vyi - b.vys[t], dvz = vzi - b.vzs[t];
+        const double dvx = a.vx - o.vx, dvy = a.vy - o.vy, dvz = a.vz - o.vz;
         const double rv = dx * dvx + dy * dvy + dz * dvz;
         double nu = 0.0;
         if (rv < 0.0) {
             const double mu = hij * rv / (r2 + eta * hij * hij);
-            nu = mu * (beta * mu - alpha * 0.5 * (ci + b.c_s[t])) / (0.5 * (rhoi + b.rho_s[t]));
+            nu = mu * (beta * mu - alpha * 0.5 * (a.c + o.c)) / (0.5 * (a.rho + o.rho));
         }
-        const double Pij = Pi_ + b.P_s[t] + nu;
+        const double Pij = a.P + o.P + nu;
         // grad W_p = dW_p/dxi * r_ij / (|r_ij| h_ij) = gw * r_ij
         const double inv2 = inv * inv;
         const double gw = kgrad * q * q * (inv2 * inv2) / r;
-        const double f = b.ms[t] * Pij * gw;
+        const double f = o.m * Pij * gw;
         sx -= f * dx;
         sy -= f * dy;
         sz -= f * dz;
@@ -178,35 +179,31 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const s
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= ng) return;
-    const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s];
-    const float hi = b.hs_f[s];
-    const float vxi = b.vx_f[s], vyi = b.vy_f[s], vzi = b.vz_f[s];
-    const float Pi_ = b.P_f[s], ci = b.c_f[s], rhoi = b.rho_f[s];
+    const sg_frec32 a = b.f32[s];
     const float kgrad = (float)(-45.0 / (64.0 * kPi));
     kahan sx{0, 0}, sy{0, 0}, sz{0, 0}, se{0, 0};
     const int64_t e1 = b.nbr_off[s + 1];
     for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
-        const int32_t t = b.nbr_idx[e];
-        const float dx = (float)(xi - b.xs[t]), dy = (float)(yi - b.ys[t]),
-                    dz = (float)(zi - b.zs[t]);
+        const sg_frec32 o = b.f32[b.nbr_idx[e]];
+        const float dx = (float)(a.x - o.x), dy = (float)(a.y - o.y), dz = (float)(a.z - o.z);
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (r2 == 0.0f) continue;
         const float r = sqrtf(r2);
-        const float hij = 0.5f * (hi + b.hs_f[t]);
+        const float hij = 0.5f * (a.h + o.h);
         const float inv = 1.0f / hij;
         const float q = 2.0f - r * inv;
         if (q <= 0.0f) continue;
-        const float dvx = vxi - b.vx_f[t], dvy = vyi - b.vy_f[t], dvz = vzi - b.vz_f[t];
+        const float dvx = a.vx - o.vx, dvy = a.vy - o.vy, dvz = a.vz - o.vz;
         const float rv = dx * dvx + dy * dvy + dz * dvz;
         float nu = 0.0f;
         if (rv < 0.0f) {
             const float mu = hij * rv / (r2 + eta * hij * hij);
-            nu = mu * (beta * mu - alpha * 0.5f * (ci + b.c_f[t])) / (0.5f * (rhoi + b.rho_f[t]));
+            nu = mu * (beta * mu - alpha * 0.5f * (a.c + o.c)) / (0.5f * (a.rho + o.rho));
         }
-        const float Pij = Pi_ + b.P_f[t] + nu;
+        const float Pij = a.P + o.P + nu;
         const float inv2 = inv * inv;
         const float gw = kgrad * q * q * (inv2 * inv2) / r;
-        const float f = b.ms_f[t] * Pij * gw;
+        const float f = o.m * Pij * gw;
         sx.add(-f * dx);
         sy.add(-f * dy);
         sz.add(-f * dz);
@@ -218,7 +215,6 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const s
     asz[i] = sz.value();
     dedt[i] = 0.5 * se.value();
 }
-
 
 // Step control of Sec. 2.2.  CFL bound of Eq. (dt-stability) per gas slot,
 // reduced to the minimum over slots with at least one neighbour: positive
@@ -239,20 +235,19 @@ __global__ __launch_bounds__(kBlock) void k_cfl(sg_sph_bufs b, const sg_grid_dev
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double dt = __builtin_inf();
     if (s < ng && b.nbr_off[s + 1] > b.nbr_off[s]) {
-        const double xi = b.xs[s], yi = b.ys[s], zi = b.zs[s], hi = b.hs[s];
-        const double vxi = b.vxs[s], vyi = b.vys[s], vzi = b.vzs[s], ci = b.c_s[s];
+        const sg_frec64 a = b.f64[s];
         double smin = __builtin_inf(), cmax = 0.0, mumax = 0.0;
         for (int64_t e = b.nbr_off[s]; e < b.nbr_off[s + 1]; ++e) {
-            const int32_t t = b.nbr_idx[e];
-            const double dx = xi - b.xs[t], dy = yi - b.ys[t], dz = zi - b.zs[t];
+            const sg_frec64 o = b.f64[b.nbr_idx[e]];
+            const double dx = a.x - o.x, dy = a.y - o.y, dz = a.z - o.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double r = sqrt(r2);
             smin = r < smin ? r : smin;
-            const double cij = 0.5 * (ci + b.c_s[t]);
+            const double cij = 0.5 * (a.c + o.c);
             cmax = cij > cmax ? cij : cmax;
-            const double rv = dx * (vxi - b.vxs[t]) + dy * (vyi - b.vys[t]) + dz * (vzi - b.vzs[t]);
+            const double rv = dx * (a.vx - o.vx) + dy * (a.vy - o.vy) + dz * (a.vz - o.vz);
             if (rv < 0.0) {
-                const double hij = 0.5 * (hi + b.hs[t]);
+                const double hij = 0.5 * (a.h + o.h);
                 const double mu = fabs(hij * rv / (r2 + eta * hij * hij));
                 mumax = mu > mumax ? mu : mumax;
             }

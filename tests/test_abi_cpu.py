@@ -71,3 +71,23 @@ def test_create_rejects_before_device(sg):
     assert L.sg_sync(None, None) == sg.SG_EINVAL
     assert b"aligned" in L.sg_last_error(None)         # reason of the last failed create
     assert L.sg_version().startswith(b"sphgrav")
+
+
+def test_autotune_candidates_are_valid_parameters(sg):
+    from paper_1807_08116_amd import autotune
+    caps = sg.default_caps(1000, 1000)
+    for prec in (sg.SG_FP64, sg.SG_FP32C):
+        for n in (8, 8192, 262144, 2097152):
+            cands = autotune.candidates(prec, n)
+            assert cands
+            for variant, ipl, split in cands:
+                p = sg.make_params(precision=prec, grav_variant=variant, grav_ipl=ipl,
+                                   grav_split=split)
+                assert sg.workspace_bytes(p, caps) > 0, (prec, n, variant, ipl, split)
+
+
+def test_ensemble_bytes(sg):
+    L = sg.lib()
+    assert L.sg_ensemble_bytes(0, 100) == 0
+    assert L.sg_ensemble_bytes(64, 4659360) > 64 * 8
+    assert L.sg_ensemble_create(None, 0, None, 0, None) == sg.SG_EINVAL
