@@ -335,9 +335,10 @@ constexpr int kMT = 512;
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 struct f32m_lds {
-    float4 hi[2][kMT];
-    float4 lo[2][kMT];
-    float b[2][4][kMT];
+    float4 hi[2][kMT];          // (x, y, z, m) hi parts, anchor-relative
+    float4 lo[2][kMT];          // (x, y, z) lo parts
+    float4 mx[2][kMT];          // (m x, m y, m z, m) for the far-field sums
+    float b[2][4][kMT];         // B operand (-2x, -2y, -2z, |x|^2)
     int near[2][kMT / kSub];
     double out[kBlock / 64][16][9];
 };
@@ -346,7 +347,7 @@ struct f32m_lds {
 // [j0, j1).  Outputs go to particle order (order[]) at ox[w + t] etc.,
 // w = out_off; raw sums unless final_out.
 template <bool POT>
-__device__ void f32m_task(f32m_lds& L, const double* __restrict__ xs,
+__device__ __attribute__((always_inline)) inline void f32m_task(f32m_lds& L, const double* __restrict__ xs,
                           const double* __restrict__ ys, const double* __restrict__ zs,
                           const double* __restrict__ ms, const box6* __restrict__ sbox,
                           const int32_t* __restrict__ order, int64_t n, int64_t ib, int64_t j0,
@@ -356,6 +357,7 @@ __device__ void f32m_task(f32m_lds& L, const double* __restrict__ xs,
     auto& s_hi = L.hi;
     auto& s_lo = L.lo;
     auto& s_b = L.b;
+    auto& s_mx = L.mx;
     auto& s_near = L.near;
     auto& s_out = L.out;
     const int tid = threadIdx.x;
@@ -414,6 +416,7 @@ __device__ void f32m_task(f32m_lds& L, const double* __restrict__ xs,
             }
             s_hi[buf][jl] = h;
             s_lo[buf][jl] = l;
+            s_mx[buf][jl] = make_float4(h.w * h.x, h.w * h.y, h.w * h.z, h.w);
             s_b[buf][0][jl] = -2.0f * h.x;
             s_b[buf][1][jl] = -2.0f * h.y;
             s_b[buf][2][jl] = -2.0f * h.z;
@@ -453,22 +456,21 @@ __device__ void f32m_task(f32m_lds& L, const double* __restrict__ xs,
                     if (POT) np += mr;
                 }
             } else {
-#pragma unroll
+#pragma unroll 2
                 for (int c = 0; c < kSub / 16; ++c) {
                     const int jl = sb * kSub + c * 16 + col;
-                    const float b = s_b[cur][grp][sb * kSub + c * 16 + col];
+                    const float b = s_b[cur][grp][jl];
                     const v4f d = __builtin_amdgcn_mfma_f32_16x16x4f32(a_op, b, cop, 0, 0, 0);
-                    const float4 q = s_hi[cur][jl];
+                    const float4 q = s_mx[cur][jl];           // (m x, m y, m z, m) of source jl
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float rinv = __builtin_amdgcn_rsqf(d[r]);
-                        const float mr = q.w * rinv;
-                        const float sv = mr * (rinv * rinv);
-                        fx[r] = __builtin_fmaf(sv, q.x, fx[r]);
-                        fy[r] = __builtin_fmaf(sv, q.y, fy[r]);
-                        fz[r] = __builtin_fmaf(sv, q.z, fz[r]);
-                        f1[r] += sv;
-                        if (POT) fp[r] += mr;
+                        const float rinv3 = (rinv * rinv) * rinv;
+                        fx[r] = __builtin_fmaf(rinv3, q.x, fx[r]);
+                        fy[r] = __builtin_fmaf(rinv3, q.y, fy[r]);
+                        fz[r] = __builtin_fmaf(rinv3, q.z, fz[r]);
+                        f1[r] = __builtin_fmaf(rinv3, q.w, f1[r]);
+                        if (POT) fp[r] = __builtin_fmaf(rinv, q.w, fp[r]);
                     }
                 }
             }
