@@ -141,9 +141,9 @@ def main():
     ap.add_argument("--only", choices=["fp32c", "fp64", "both"], default="both")
     ap.add_argument("--ipl", type=int, default=0, help="gravity targets per lane (0 = auto)")
     ap.add_argument("--split", type=int, default=0, help="gravity source splits (0 = auto)")
+    ap.add_argument("--tile", type=int, default=0, help="gravity sources per LDS tile (0 = auto)")
     ap.add_argument("--variant", type=int, default=0,
-                    help="gravity kernel: 0 automatic; FP64 1 FP32-seeded rsqrt, 2 FP64-seeded; "
-                         "FP32C 1 vector ALU, 2 matrix-core far field")
+                    help="FP64 gravity kernel: 0 automatic, 1 FP32-seeded rsqrt, 2 FP64-seeded")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -170,7 +170,8 @@ def main():
     for form in forms:
         p = sg.SG_FP32C if form == "fp32c" else sg.SG_FP64
         log("timing %s: %d warmup + %d steps" % (form, args.warmup, args.steps))
-        tune = dict(grav_ipl=args.ipl, grav_split=args.split, grav_variant=args.variant)
+        tune = dict(grav_ipl=args.ipl, grav_split=args.split, grav_tile=args.tile,
+                    grav_variant=args.variant if p == sg.SG_FP64 else 0)
         res[form] = run_form(sg, st, p, args.steps, args.warmup, sample, tune)
         log("  %s: %.3f s/step" % (form, res[form]["sec"] / args.steps))
 

@@ -72,21 +72,31 @@ typedef enum {
  * alpha, beta, eta: artificial-viscosity constants (Sec. 2.2), >= 0, eta > 0.
  * precision: an sg_precision value.
  * grav_ipl: target particles per GPU lane in the gravity kernel (1, 2 or 4;
- *   0 = automatic).  grav_split: number of source-range splits (>= 1;
- *   0 = automatic).  Neither changes results beyond summation order.
+ *   0 = automatic); a workgroup of 256 lanes owns 256 * grav_ipl targets.
+ *   grav_split: number of source-range splits (>= 1; 0 = automatic).
+ *   grav_tile: sources per LDS tile of the gravity kernels (128, 256 or
+ *   512; 0 = automatic, 256).  None of the three changes results beyond
+ *   summation order.
  * grav_variant: 0 = automatic.  FP64 form: 1 = reciprocal square root
  *   seeded in FP32 and refined in FP64 (needs eps^2 >= 1.2e-38; the
  *   automatic choice), 2 = seeded in FP64 (both refined to FP64 rounding
- *   level).  FP32C form: 1 = all pairs on the vector ALU (the automatic
- *   choice), 2 = far-field squared separations on the matrix cores (MFMA;
- *   required by ensembles). */
+ *   level).  FP32C form: 1 (the only kernel).
+ * cell_scale_log2: side of the neighbour-search cells relative to the
+ *   default rule, as a power of two (-1, 0 or +1; 0 = default).  Each gas
+ *   particle keeps its level (the first l with L0 * 2^l >= (2 + 2^-9) h_i,
+ *   L0 the smallest power of two >= (2 + 2^-9) min h); level-l cells get the
+ *   side L0 * 2^(l + cell_scale_log2).  It changes cell keys, counts,
+ *   offsets and the slot order (so the exported grid arrays and the order
+ *   of SPH sums), never which particles are neighbours. */
 typedef struct {
     double G, eps, gamma, alpha, beta, eta;
     int32_t precision;
     int32_t grav_ipl;
     int32_t grav_split;
     int32_t grav_variant;
-    int32_t reserved[4];        /* must be zero */
+    int32_t grav_tile;
+    int32_t cell_scale_log2;
+    int32_t reserved[2];        /* must be zero */
 } sg_params;
 
 /* Capacities the workspace is sized for.
@@ -213,7 +223,8 @@ typedef enum {
     SG_X_GORDER = 8     /* int32 [N] gravity target order (SG_FP32C only)    */
 } sg_export_what;
 
-/* Host-readable grid description (SG_X_GRID). */
+/* Host-readable grid description (SG_X_GRID): L0 is the base of the level
+ * rule (see cell_scale_log2), L[l] the cell side of level l. */
 typedef struct {
     double L0;
     int32_t nlev, pad;
@@ -238,10 +249,12 @@ sg_status sg_export(sg_ctx *ctx, int32_t what, void *d_dst, int64_t cap_bytes,
  * required (need may be NULL). */
 sg_status sg_sync(sg_ctx *ctx, int64_t need[2]);
 
-/* Ensembles of independent systems (one bound context each, all SG_FP32C
- * with grav_variant 2, the same G, eps and stream).  Gravity of all systems
- * runs as ONE persistent launch: workgroups take (system, 64-target block)
- * tasks, largest systems first, from a device counter until none is left.
+/* Ensembles of independent systems (one bound context each, all SG_FP32C,
+ * the same G, eps and stream).  Gravity of all systems runs as ONE
+ * persistent launch: workgroups take (system, block of 256 * grav_ipl
+ * targets) tasks, largest systems first, from a device counter until none
+ * is left; grav_ipl and grav_tile (resolved as for sg_compute_accel) are
+ * those of the first context.
  * The ensemble keeps pointers into the contexts: do not rebind or destroy
  * them while it exists.  d_ws: caller-owned device memory of
  * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task

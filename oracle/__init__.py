@@ -93,7 +93,7 @@ def lib():
         L.or_pred.restype = C.c_int
         L.or_pred.argtypes = [_dbl] * 8
         L.or_grid.restype = C.c_int
-        L.or_grid.argtypes = [_i64, _D, _D, _D, _D, C.POINTER(Grid)]
+        L.or_grid.argtypes = [_i64, _D, _D, _D, _D, C.c_int, C.POINTER(Grid)]
         L.or_keys.restype = None
         L.or_keys.argtypes = [_i64, _D, _D, _D, _D, C.POINTER(Grid), _I32, _opt(_I32)]
         L.or_count_sort.restype = None
@@ -161,9 +161,9 @@ def pred(pi, hi, pj, hj):
 # Grid, keys, counting sort
 # --------------------------------------------------------------------------
 
-def grid(x, y, z, h):
+def grid(x, y, z, h, cell_scale_log2=0):
     g = Grid()
-    rc = lib().or_grid(len(x), _c(x), _c(y), _c(z), _c(h), C.byref(g))
+    rc = lib().or_grid(len(x), _c(x), _c(y), _c(z), _c(h), int(cell_scale_log2), C.byref(g))
     if rc != 0:
         raise ValueError("oracle grid error %d" % rc)
     return g
@@ -201,9 +201,9 @@ def count_sort(key, h, M):
     return count, off, hmax, perm
 
 
-def sort_gas(x, y, z, h):
+def sort_gas(x, y, z, h, cell_scale_log2=0):
     """Grid, keys, counts, offsets, hmax and stable permutation of the gas."""
-    g = grid(x, y, z, h)
+    g = grid(x, y, z, h, cell_scale_log2)
     key, lev = keys(x, y, z, h, g)
     count, off, hmax, perm = count_sort(key, h, g.M)
     return {"grid": g, "key": key, "level": lev, "count": count, "off": off,

@@ -98,7 +98,10 @@ int or_pred(double xi, double yi, double zi, double hi,
  * a particle lives on the first level with L_l >= (2 + 2^-9) h_i.  Each
  * non-empty level spans the bounding box of its own particles, with origin
  * floor(min/L_l) L_l and M_d = floor((max - origin)/L_l) + 1 cells along d.
- * Cells are numbered level by level, then z, y, x (x fastest). */
+ * Cells are numbered level by level, then z, y, x (x fastest).  A cell-size
+ * scale 2^s (s = cell_scale_log2 in {-1, 0, 1}, a tuning choice of the
+ * search, not of the method) multiplies every cell side, L_l = L_0 2^(l+s),
+ * while the level of each particle is still decided by L_0 2^l. */
 typedef struct {
     double L0;
     int32_t nlev;                   /* levels 0..nlev-1 (some may be empty) */
@@ -139,7 +142,7 @@ static int or_level_of(double h, double L0)
 /* Returns 0 on success, -1 if a level beyond OR_MAX_LEVELS is needed,
  * -2 if the cell count overflows 2^31-1, -3 on empty input. */
 int or_grid(int64_t ng, const double *x, const double *y, const double *z,
-            const double *h, or_grid_t *g)
+            const double *h, int cell_scale_log2, or_grid_t *g)
 {
     memset(g, 0, sizeof(*g));
     if (ng <= 0)
@@ -151,7 +154,7 @@ int or_grid(int64_t ng, const double *x, const double *y, const double *z,
     g->L0 = or_pow2_ceil(hmin * (2.0 + 0x1p-9));
     double lo[OR_MAX_LEVELS][3], hi[OR_MAX_LEVELS][3];
     for (int l = 0; l < OR_MAX_LEVELS; l++) {
-        g->L[l] = ldexp(g->L0, l);
+        g->L[l] = ldexp(g->L0, l + cell_scale_log2);
         g->hmax[l] = 0.0;
         for (int d = 0; d < 3; d++) {
             lo[l][d] = INFINITY;

@@ -16,13 +16,14 @@ namespace {
 thread_local char g_create_msg[256] = "null context";
 
 // grav_variant 0 (automatic) resolved per precision form: FP64 -> 1 (rsqrt
-// seeded in FP32); FP32C -> 1 (all pairs on the vector ALU).
+// seeded in FP32); FP32C has one kernel (1).
 constexpr int kAutoVariantFP64 = 1;
-constexpr int kAutoVariantFP32C = 1;
 inline int resolved_variant(const sg_params& p) {
-    if (p.grav_variant != 0) return p.grav_variant;
-    return p.precision == SG_FP32C ? kAutoVariantFP32C : kAutoVariantFP64;
+    if (p.precision == SG_FP32C) return 1;
+    return p.grav_variant != 0 ? p.grav_variant : kAutoVariantFP64;
 }
+// grav_tile 0 (automatic): 256 sources per LDS tile.
+inline int resolved_tile(const sg_params& p) { return p.grav_tile != 0 ? p.grav_tile : 256; }
 
 constexpr size_t kAlign = 256;
 inline size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -112,10 +113,16 @@ bool params_ok(const sg_params* p, const char** why) {
     if (p->grav_ipl != 0 && p->grav_ipl != 1 && p->grav_ipl != 2 && p->grav_ipl != 4)
         return *why = "grav_ipl must be 0, 1, 2 or 4", false;
     if (p->grav_split < 0 || p->grav_split > 64) return *why = "grav_split must be in [0, 64]", false;
-    if (p->grav_variant < 0 || p->grav_variant > 2)
-        return *why = "grav_variant must be 0, 1 or 2", false;
-    if (p->precision == SG_FP64 && p->grav_variant != 2 && !(p->eps * p->eps >= 1.2e-38))
-        return *why = "FP32-seeded FP64 gravity needs eps^2 in the FP32 normal range", false;
+    if (p->precision == SG_FP64 && (p->grav_variant < 0 || p->grav_variant > 2))
+        return *why = "grav_variant must be 0, 1 or 2 in the FP64 form", false;
+    if (p->precision == SG_FP32C && p->grav_variant != 0 && p->grav_variant != 1)
+        return *why = "grav_variant must be 0 or 1 in the FP32C form", false;
+    if (p->grav_tile != 0 && p->grav_tile != 128 && p->grav_tile != 256 && p->grav_tile != 512)
+        return *why = "grav_tile must be 0, 128, 256 or 512", false;
+    if (p->cell_scale_log2 < -1 || p->cell_scale_log2 > 1)
+        return *why = "cell_scale_log2 must be -1, 0 or 1", false;
+    if ((p->precision == SG_FP32C || p->grav_variant != 2) && !(p->eps * p->eps >= 1.2e-38))
+        return *why = "FP32 pair arithmetic needs eps^2 in the FP32 normal range", false;
     for (int r : p->reserved)
         if (r != 0) return *why = "reserved fields must be zero", false;
     return true;
@@ -239,17 +246,23 @@ sg_status need_bound(sg_ctx* c) {
     return SG_OK;
 }
 
-// Automatic gravity launch shape: enough workgroups to cover the 256 CUs
-// several times over, targets per lane as large as that allows.
+// Automatic targets per lane: as many as keep enough workgroups to cover
+// the 256 CUs several times over.  The FP32C kernel stops at 2: at 4 its
+// register footprint (about 200 VGPRs) leaves 2 wavefronts per SIMD, and it
+// measured slower than with 2 targets (4 wavefronts per SIMD).
+int auto_ipl(int precision, int64_t n) {
+    int p = n >= 4 * 256 * 2048 ? 4 : (n >= 2 * 256 * 1024 ? 2 : 1);
+    if (precision == SG_FP32C && p > 2) p = 2;
+    return p;
+}
+
+// Automatic gravity launch shape (targets per lane, source splits).
 void grav_shape(const sg_ctx* c, int* ipl, int* split) {
     const int64_t n = c->n;
     int p = c->prm.grav_ipl;
-    if (p == 0) p = n >= 4 * 256 * 2048 ? 4 : (n >= 2 * 256 * 1024 ? 2 : 1);
+    if (p == 0) p = auto_ipl(c->prm.precision, n);
     int s = c->prm.grav_split;
-    // targets per workgroup: 256 * ipl (vector-ALU kernels) or 64 (FP32C
-    // with the far field on the matrix cores)
-    const bool mfma = c->prm.precision == SG_FP32C && resolved_variant(c->prm) == 2;
-    const int64_t per = mfma ? 64 : 256 * p;
+    const int64_t per = 256 * p;                 // targets per workgroup
     const int64_t iblocks = (n + per - 1) / per;
     if (s == 0) {
         int64_t want = (2048 + iblocks - 1) / iblocks;
@@ -281,7 +294,7 @@ sg_status do_build(sg_ctx* c) {
     c->begin(SG_ST_SORT);
     sg_launch_grid_reset(g, st);
     sg_launch_grid_reduce(s.x, s.y, s.z, s.h, ng, g, st);
-    sg_launch_grid_finish(g, C, st);
+    sg_launch_grid_finish(g, C, c->prm.cell_scale_log2, st);
     sg_launch_cells_clear(g, count, hmax, cursor, C, st);
     sg_launch_keys_count(s.x, s.y, s.z, s.h, ng, g, key, count, hmax, st);
     sg_launch_scan(count, off, 0, &g->M, C, scan, st);
@@ -329,6 +342,7 @@ void grav_args(sg_ctx* c, bool pot, sg_grav_args& a) {
     a.eps = c->prm.eps;
     a.precision = c->prm.precision;
     grav_shape(c, &a.ipl, &a.split);
+    a.tile = resolved_tile(c->prm);
     a.with_pot = pot ? 1 : 0;
     a.variant = resolved_variant(c->prm);
     a.order = c->prm.precision == SG_FP32C ? c->at<int32_t>(c->L.gorder) : nullptr;
@@ -768,7 +782,7 @@ struct sg_ens {
     sg_ens_task* d_tasks;
     int32_t* d_counter;
     int32_t ntasks;
-    int nblocks;
+    int nblocks, ipl, tile;
     double eps, G;
     char msg[256];
     sg_status fail(sg_status code, const char* m) {
@@ -798,7 +812,7 @@ sg_status ens_gravity(sg_ens* e, bool pot) {
     sg_ctx* c0 = e->c[0];
     c0->begin(SG_ST_GRAV);
     sg_launch_grav_ensemble(e->d_sys, e->d_tasks, e->ntasks, e->d_counter, pot ? 1 : 0, e->eps,
-                            e->G, e->nblocks, e->st);
+                            e->G, e->ipl, e->tile, e->nblocks, e->st);
     c0->end();
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return e->fail(SG_EDEVICE, hipGetErrorString(err));
@@ -855,10 +869,16 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
     std::vector<sg_ens_sys> sys((size_t)nsys);
     std::vector<std::pair<int64_t, sg_ens_task>> tasks;
     int64_t total = 0;
+    if (!ctxs[0] || !ctxs[0]->bound) return SG_EINVAL;
+    // launch shape of the first context: 256 * ipl targets per task
+    const int ipl = ctxs[0]->prm.grav_ipl != 0 ? ctxs[0]->prm.grav_ipl
+                                               : auto_ipl(SG_FP32C, ctxs[0]->n);
+    const int tile = resolved_tile(ctxs[0]->prm);
+    const int64_t per = 256 * (int64_t)ipl;
     for (int32_t k = 0; k < nsys; ++k) {
         sg_ctx* c = ctxs[k];
         if (!c || !c->bound) return SG_EINVAL;
-        if (c->prm.precision != SG_FP32C || resolved_variant(c->prm) != 2) return SG_EINVAL;
+        if (c->prm.precision != SG_FP32C) return SG_EINVAL;
         if (c->st != ctxs[0]->st || c->prm.G != ctxs[0]->prm.G || c->prm.eps != ctxs[0]->prm.eps)
             return SG_EINVAL;
         sg_ens_sys& S = sys[(size_t)k];
@@ -869,7 +889,7 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
         S.gy = c->at<double>(c->L.gy);
         S.gz = c->at<double>(c->L.gz);
         S.gp = c->s.pot ? c->s.pot : c->at<double>(c->L.gpot);
-        const int64_t nb = (c->n + 63) / 64;
+        const int64_t nb = (c->n + per - 1) / per;
         for (int64_t b = 0; b < nb; ++b) tasks.push_back({c->n, sg_ens_task{k, (int32_t)b}});
         total += c->n;
     }
@@ -891,13 +911,18 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
     e->d_tasks = (sg_ens_task*)(ws + o_tasks);
     e->d_counter = (int32_t*)(ws + o_counter);
     e->ntasks = (int32_t)tk.size();
+    e->ipl = ipl;
+    e->tile = tile;
     e->eps = ctxs[0]->prm.eps;
     e->G = ctxs[0]->prm.G;
     e->msg[0] = 0;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    e->nblocks = 3 * (cus > 0 ? cus : 256);
+    // persistent grid: as many workgroups as are resident at once
+    const int per_cu = sg_grav_ensemble_blocks_per_cu(ipl, tile, 1);
+    (void)hipGetLastError();
+    e->nblocks = per_cu * (cus > 0 ? cus : 256);
     if (e->nblocks > e->ntasks) e->nblocks = e->ntasks;
     if (hipMemcpyAsync(e->d_sys, sys.data(), sizeof(sg_ens_sys) * sys.size(), hipMemcpyHostToDevice,
                        e->st) != hipSuccess ||

@@ -68,7 +68,7 @@ void sg_launch_grid_reset(sg_grid_dev* g, hipStream_t st);   // keeps the error 
 void sg_launch_status_clear(sg_grid_dev* g, hipStream_t st);
 void sg_launch_grid_reduce(const double* x, const double* y, const double* z, const double* h,
                            int64_t ng, sg_grid_dev* g, hipStream_t st);
-void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, hipStream_t st);
+void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, int cell_scale_log2, hipStream_t st);
 void sg_launch_cells_clear(sg_grid_dev* g, int32_t* count, unsigned long long* hmax,
                            int32_t* cursor, int64_t cell_cap, hipStream_t st);
 void sg_launch_keys_count(const double* x, const double* y, const double* z, const double* h,
@@ -139,8 +139,9 @@ struct sg_grav_args {
     int64_t n;
     double G, eps;
     int precision, ipl, split, with_pot;
+    int tile;                           // sources per LDS tile: 128, 256 or 512
     int variant;                        // resolved: FP64 1 = FP32-seeded rsqrt, 2 = FP64-seeded;
-                                        // FP32C 1 = vector ALU, 2 = matrix-core far field
+                                        // FP32C 1 (the only one)
     const int32_t* order;               // FP32C: Morton order of the particles, else null
     void* sorted;                       // FP32C: scratch of sg_grav_sorted_bytes(n)
     const double *xs, *ys, *zs, *ms;    // (set by the launcher) sorted copies
@@ -155,8 +156,8 @@ size_t sg_grav_sorted_bytes(int64_t n);
 int sg_launch_grav_sorted(const sg_grav_args& a, hipStream_t st);
 int sg_launch_gravity(const sg_grav_args& a, hipStream_t st);
 
-// Ensembles: one persistent launch over (system, 64-target block) tasks of
-// several systems in the FP32C form with the matrix-core far field.
+// Ensembles: one persistent launch over (system, block of 256*ipl targets)
+// tasks of several systems in the FP32C form.
 struct sg_ens_sys {
     const double *xs, *ys, *zs, *ms;    // Morton-sorted copies
     const void* sbox;                   // 64-particle boxes
@@ -170,8 +171,10 @@ struct sg_ens_task {
 void sg_grav_sorted_ptrs(void* sorted, int64_t n, const double** xs, const double** ys,
                          const double** zs, const double** ms, const void** sbox);
 void sg_launch_grav_ensemble(const sg_ens_sys* d_sys, const sg_ens_task* d_tasks, int32_t ntasks,
-                             int32_t* d_counter, int with_pot, double eps, double G, int nblocks,
-                             hipStream_t st);
+                             int32_t* d_counter, int with_pot, double eps, double G, int ipl,
+                             int tile, int nblocks, hipStream_t st);
+// Workgroups of the ensemble kernel that fit on one CU at once (>= 1).
+int sg_grav_ensemble_blocks_per_cu(int ipl, int tile, int with_pot);
 
 // Spatial (Morton) order of all N particles for the FP32C gravity targets.
 size_t sg_morton_tmp_bytes(int64_t n);

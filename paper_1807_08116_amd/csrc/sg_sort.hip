@@ -286,7 +286,9 @@ __global__ __launch_bounds__(kBlock) void k_grid_levels(const double* __restrict
     }
 }
 
-__global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap) {
+// Cell sides L[l] = L0 2^(l + cell_scale_log2) (powers of two); the level of
+// a particle depends on L0 only.
+__global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap, double cell_scale) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (g->err & (SGE_NONFINITE | SGE_LEVELS)) {
         g->M = 0;
@@ -300,7 +302,7 @@ __global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap) {
         if (g->npart[l]) nlev = l + 1;
     g->nlev = nlev;
     int64_t M = 0;
-    double L = L0;
+    double L = L0 * cell_scale;        // exact: cell_scale is 1/2, 1 or 2
     for (int l = 0; l < SG_MAXLEV; ++l, L *= 2.0) {
         g->L[l] = L;
         g->invL[l] = 1.0 / L;          // exact: L is a power of two
@@ -619,8 +621,9 @@ void sg_launch_grid_reduce(const double* x, const double* y, const double* z, co
     hipLaunchKernelGGL(k_grid_levels, dim3(nb), dim3(kBlock), 0, st, x, y, z, h, ng, g);
 }
 
-void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, hipStream_t st) {
-    hipLaunchKernelGGL(k_grid_finish, dim3(1), dim3(64), 0, st, g, cell_cap);
+void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, int cell_scale_log2, hipStream_t st) {
+    const double scale = cell_scale_log2 < 0 ? 0.5 : (cell_scale_log2 > 0 ? 2.0 : 1.0);
+    hipLaunchKernelGGL(k_grid_finish, dim3(1), dim3(64), 0, st, g, cell_cap, scale);
 }
 
 void sg_launch_cells_clear(sg_grid_dev* g, int32_t* count, unsigned long long* hmax,

@@ -7,8 +7,11 @@ FP32-compensated form.  Reports aggregate pair-interactions/s of the
 batched gravity and of per-system launches, and steps/s of graph-captured
 ensemble steps.
 
+With --tune the persistent launch's targets per lane and j-tile are first
+picked by the autotuner on these systems.
+
 Usage: python -m paper_1807_08116_amd.ensemble [--nsys 64] [--steps 50]
-           [--reps 3] [--scale 1.0]
+           [--reps 3] [--scale 1.0] [--tune]
 """
 import argparse
 import json
@@ -29,6 +32,7 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--tune", action="store_true")
     args = ap.parse_args()
     import torch
     from paper_1807_08116_amd import ic
@@ -40,7 +44,13 @@ def main():
     pairs = float(np.sum(ns * ns))
     log("inputs: %d systems, %d particles, %.3e pairs per gravity pass (%.1fs)"
         % (len(states), int(ns.sum()), pairs, time.perf_counter() - t))
-    ens = sg.Ensemble(states)
+    shape = {}
+    if args.tune:
+        from paper_1807_08116_amd import autotune
+        t = time.perf_counter()
+        shape = autotune.tune_ensemble(states, reps=2, verbose=True)
+        log("autotuned ensemble launch %s (%.1fs)" % (shape, time.perf_counter() - t))
+    ens = sg.Ensemble(states, **shape)
     st = ens.stream
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
@@ -78,6 +88,7 @@ def main():
         "one_by_one_gravity_ms": ms_single, "one_by_one_pairs_per_s": pairs / ms_single * 1e3,
         "batched_speedup": ms_single / ms_batched,
         "steps": args.steps, "steps_per_s": args.steps / sec, "graph": True, "precision": "fp32c",
+        "launch": shape or "automatic",
     }
     print(json.dumps(out), flush=True)
 

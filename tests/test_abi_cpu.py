@@ -39,10 +39,16 @@ def test_workspace_validation(sg):
     assert sg.workspace_bytes(good, caps) > 0
     for bad in (dict(eps=0.0), dict(eps=-1.0), dict(gamma=1.0), dict(alpha=-1.0),
                 dict(eta=0.0), dict(precision=7), dict(grav_ipl=3), dict(grav_split=65),
-                dict(G=float("nan")), dict(grav_variant=3), dict(eps=1e-20)):
+                dict(G=float("nan")), dict(grav_variant=3), dict(eps=1e-20),
+                dict(precision=1, grav_variant=2), dict(precision=1, eps=1e-20),
+                dict(grav_tile=64), dict(grav_tile=1024), dict(cell_scale_log2=2),
+                dict(cell_scale_log2=-2)):
         assert sg.workspace_bytes(sg.make_params(**bad), caps) == 0, bad
+    for ok in (dict(grav_tile=128), dict(grav_tile=512), dict(cell_scale_log2=-1),
+               dict(cell_scale_log2=1), dict(grav_variant=2, eps=1e-20)):
+        assert sg.workspace_bytes(sg.make_params(**ok), caps) > 0, ok
     p = sg.make_params()
-    p.reserved[2] = 1
+    p.reserved[1] = 1
     assert sg.workspace_bytes(p, caps) == 0
     assert sg.workspace_bytes(good, sg.Caps(0, 0, 0, 0)) == 0
     assert sg.workspace_bytes(good, sg.Caps(-1, 5, 5, 5)) == 0
@@ -80,10 +86,11 @@ def test_autotune_candidates_are_valid_parameters(sg):
         for n in (8, 8192, 262144, 2097152):
             cands = autotune.candidates(prec, n)
             assert cands
-            for variant, ipl, split in cands:
-                p = sg.make_params(precision=prec, grav_variant=variant, grav_ipl=ipl,
-                                   grav_split=split)
-                assert sg.workspace_bytes(p, caps) > 0, (prec, n, variant, ipl, split)
+            for cand in cands:
+                p = sg.make_params(precision=prec, **cand)
+                assert sg.workspace_bytes(p, caps) > 0, (prec, n, cand)
+    for s_ in autotune.CELL_SCALES:
+        assert sg.workspace_bytes(sg.make_params(cell_scale_log2=s_), caps) > 0
 
 
 def test_ensemble_bytes(sg):

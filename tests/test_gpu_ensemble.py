@@ -1,6 +1,7 @@
 """Ensembles: gravity of several systems in one persistent launch equals
-each system's own gravity; ensemble steps equal per-system steps; graph
-replays equal eager ensemble steps."""
+each system's own gravity (same kernel body, same targets per workgroup);
+ensemble steps equal per-system steps; graph replays equal eager ensemble
+steps."""
 import numpy as np
 import pytest
 
@@ -27,12 +28,13 @@ def states():
     return ic.ensemble(nsys=5, scale=0.05)          # 5 systems of ~400..13000 particles
 
 
-def test_ensemble_gravity_matches_single(sg, orc, states):
-    ens = sg.Ensemble(states)
+@pytest.mark.parametrize("ipl,tile", [(2, 256), (1, 128), (4, 512)])
+def test_ensemble_gravity_matches_single(sg, orc, states, ipl, tile):
+    ens = sg.Ensemble(states, grav_ipl=ipl, grav_tile=tile)
     ens.gravity(sg.SG_GRAV | sg.SG_POT)
     ens.torch.cuda.synchronize()
     for st, eng in zip(states, ens.engines):
-        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_variant=2)
+        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_ipl=ipl, grav_tile=tile)
         single.ctx.compute_accel(sg.SG_GRAV | sg.SG_POT)
         single.ctx.sync()
         for f in ("ax", "ay", "az", "pot"):
@@ -47,12 +49,12 @@ def test_ensemble_gravity_matches_single(sg, orc, states):
 
 def test_ensemble_steps_match_single_and_graph(sg, states):
     dt = 1e-3
-    eager = sg.Ensemble(states)
+    eager = sg.Ensemble(states, grav_ipl=2)
     eager.run(dt, 4, sg.SG_POT, use_graph=False)
-    graph = sg.Ensemble(states)
+    graph = sg.Ensemble(states, grav_ipl=2)
     graph.run(dt, 4, sg.SG_POT, use_graph=True)
     for st, e1, e2 in zip(states, eager.engines, graph.engines):
-        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_variant=2)
+        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_ipl=2)
         for _ in range(4):
             single.ctx.step(dt, sg.SG_POT)
         single.ctx.sync()

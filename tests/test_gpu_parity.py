@@ -101,6 +101,27 @@ def test_c0_sort_and_neighbours_bitexact(sg, orc, c0, c0_ref):
     check_sort_bitexact(sg, eng, s, soff, sidx, orc)
 
 
+@pytest.mark.parametrize("scale", [-1, 1])
+def test_c0_cell_scale_bitexact(sg, orc, c0, c0_ref, scale):
+    # another cell size: keys, counts, offsets, permutation and rows follow
+    # the oracle's grid at the same scale; the neighbour pairs are the same
+    ref, s0, soff0, sidx0 = c0_ref
+    ng = c0["ng"]
+    x, y, z, h = c0["x"][:ng], c0["y"][:ng], c0["z"][:ng], c0["h"]
+    s = orc.sort_gas(x, y, z, h, cell_scale_log2=scale)
+    soff, sidx = orc.rows_to_slots(s["perm"], *orc.nbrs(x, y, z, h))
+    eng = sg.Engine(c0, precision=sg.SG_FP64, cell_scale_log2=scale)
+    eng.build_neighbors()
+    check_sort_bitexact(sg, eng, s, soff, sidx, orc)
+    assert s["grid"].L[0] == s0["grid"].L[0] * 2.0 ** scale
+    assert len(sidx) == len(sidx0)
+    eng.ctx.compute_density()
+    eng.ctx.compute_accel(sg.SG_SPH | sg.SG_GRAV | sg.SG_POT)
+    eng.ctx.sync()
+    assert nrm_err(eng.numpy("rho")[:ng], ref["rho"]) < FP64_TOL
+    assert nrm_err(gpu_accel(eng), oracle_accel(orc, c0, ref)) < FP64_TOL
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_c0_forces(sg, orc, c0, c0_ref, precision):
     ref, s, soff, sidx = c0_ref
@@ -120,12 +141,16 @@ def test_c0_forces(sg, orc, c0, c0_ref, precision):
     assert e_pot < tol
 
 
-@pytest.mark.parametrize("ipl,split,variant", [(1, 1, 0), (2, 3, 1), (4, 1, 2), (4, 1, 1),
-                                               (1, 64, 2), (4, 7, 1), (0, 0, 2), (0, 5, 2)])
-def test_gravity_launch_shapes(sg, orc, c0, c0_ref, ipl, split, variant):
+# (targets per lane, source splits, FP64 variant, j-tile); the FP32C form
+# has one kernel and takes the same shapes with variant 0
+@pytest.mark.parametrize("ipl,split,variant,tile", [
+    (1, 1, 0, 0), (2, 3, 1, 128), (4, 1, 2, 512), (4, 1, 1, 256), (1, 64, 2, 128),
+    (4, 7, 1, 512), (0, 0, 2, 0), (0, 5, 2, 512), (2, 1, 1, 512), (2, 2, 0, 128)])
+def test_gravity_launch_shapes(sg, orc, c0, c0_ref, ipl, split, variant, tile):
     ref, *_ = c0_ref
     for p in (sg.SG_FP64, sg.SG_FP32C):
-        eng = sg.Engine(c0, precision=p, grav_ipl=ipl, grav_split=split, grav_variant=variant)
+        eng = sg.Engine(c0, precision=p, grav_ipl=ipl, grav_split=split, grav_tile=tile,
+                        grav_variant=variant if p == sg.SG_FP64 else 0)
         eng.ctx.compute_accel(sg.SG_GRAV | sg.SG_POT)
         eng.ctx.sync()
         g = np.stack([ref["gx"], ref["gy"], ref["gz"]], 1)

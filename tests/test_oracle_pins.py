@@ -104,10 +104,11 @@ def _clustered(rng, n):
     return pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), h
 
 
-def test_grid_rule_properties(orc):
+@pytest.mark.parametrize("scale", [0, -1, 1])
+def test_grid_rule_properties(orc, scale):
     rng = np.random.default_rng(3)
     x, y, z, h = _clustered(rng, 3000)
-    g = orc.grid(x, y, z, h)
+    g = orc.grid(x, y, z, h, scale)
     gd = orc.grid_dict(g)
     key, lev = orc.keys(x, y, z, h, g)
     t = h * (2.0 + 2.0 ** -9)
@@ -117,6 +118,9 @@ def test_grid_rule_properties(orc):
     L = L0 * 2.0 ** lev
     assert np.all(L >= t)
     assert np.all((lev == 0) | (L / 2 < t))                   # first level that fits
+    # the cell side of level l is L0 2^(l + scale); levels do not depend on it
+    np.testing.assert_array_equal(gd["L"], L0 * 2.0 ** (np.arange(gd["nlev"]) + scale))
+    np.testing.assert_array_equal(lev, orc.keys(x, y, z, h, orc.grid(x, y, z, h))[1])
     # every particle lies inside its cell
     for l in range(gd["nlev"]):
         sel = lev == l
