@@ -28,7 +28,36 @@ sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = 22          # 20 for the acceleration, +2 for the potential
 PEAK = {"fp32": 157.3, "fp64": 78.6}  # TFLOP/s, MI355X vector peaks
+HBM_PEAK = 8000.0            # GB/s
 DT = 1e-3
+
+
+def pass_bytes(stage, precision_form, ng, nnz, ncell):
+    """Algorithmic HBM bytes of one launch group of an HBM-bound stage: every
+    array the stage must read or write, counted once (per gas particle, per
+    neighbour pair, per cell)."""
+    if stage == "sort":        # x,y,z,h in; keys, perm; gather 40 B in, 104 B out; cells
+        return 192 * ng + 24 * ncell
+    if stage == "nbr":         # own x,y,z,h; count + offset; one int32 per pair
+        return 44 * ng + 4 * nnz
+    if stage == "density":     # offset, record (64 B), rho out; one index per pair
+        return 80 * ng + 4 * nnz
+    if stage == "sph":         # EOS + record build, then offsets, records, 4 outputs
+        return (336 if precision_form == "fp64" else 272) * ng + 4 * nnz
+    raise ValueError(stage)
+
+
+def hbm_passes(precision_form, prof, ng, nnz, ncell):
+    out = {}
+    for stage in ("sort", "nbr", "density", "sph"):
+        ms, launches = prof[stage]
+        if launches == 0 or ms <= 0:
+            continue
+        b = pass_bytes(stage, precision_form, ng, nnz, ncell)
+        gbs = b * launches / (ms * 1e-3) / 1e9
+        out[stage] = {"ms_per_launch": ms / launches, "bytes_per_launch": b,
+                      "achieved_GB_s": gbs, "frac_of_peak": gbs / HBM_PEAK}
+    return out
 
 
 def recorded_traffic(precision_form):
@@ -82,10 +111,13 @@ def run_form(sg, st, precision, steps, warmup, sample, tune):
     ctx.profile_enable(False)
     ctx.sync()
     d = diag.cpu().numpy()
+    nnz = int(ctx.export(sg.SG_X_NBR_OFF)[-1])
+    ncell = int(sg.grid_dict(ctx.export(sg.SG_X_GRID))["M"])
     eng.ctx.close()
     del eng
     torch.cuda.empty_cache()
-    return {"sec": (t1 - t0), "acc": acc, "prof": prof, "diag": d.tolist()}
+    return {"sec": (t1 - t0), "acc": acc, "prof": prof, "diag": d.tolist(), "nnz": nnz,
+            "ncell": ncell}
 
 
 def cpu_baseline(st, sample, prm):
@@ -225,6 +257,8 @@ def main():
             "grav_ms_per_launch": pr["grav"][0] / max(pr["grav"][1], 1),
             "accel_err": errs.get(form),
             "diagnostics_last": res[form]["diag"],
+            "nnz": res[form]["nnz"],
+            "hbm_passes": hbm_passes(form, pr, ng, res[form]["nnz"], res[form]["ncell"]),
         }
     if "fp64" in res and "fp32c" in res:
         out["fp32c_vs_fp64_speedup"] = res["fp64"]["sec"] / res["fp32c"]["sec"]

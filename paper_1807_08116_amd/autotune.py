@@ -35,9 +35,9 @@ CELL_SCALES = (-1, 0, 1)
 
 
 def _fill_split(n, ipl):
-    """Splits that give about 2048 workgroups (the library's automatic rule)."""
+    """Splits that give about 8192 workgroups (the library's automatic rule)."""
     blocks = max(1, (n + 256 * ipl - 1) // (256 * ipl))
-    return max(1, min(64, (2048 + blocks - 1) // blocks))
+    return max(1, min(64, (8192 + blocks - 1) // blocks))
 
 
 def candidates(precision, n):
@@ -47,7 +47,7 @@ def candidates(precision, n):
     variants = (1, 2) if precision == sg.SG_FP64 else (0,)
     for ipl in IPLS:
         for tile in TILES:
-            for split in sorted({1, 2, _fill_split(n, ipl)}):
+            for split in sorted({1, 2, 4, _fill_split(n, ipl)}):
                 for v in variants:
                     out.append(dict(grav_ipl=ipl, grav_tile=tile, grav_split=split, grav_variant=v))
     return out
@@ -117,7 +117,7 @@ def tune_gravity(st, precision, reps=2, path=CACHE, verbose=False):
     try_axis("grav_ipl", IPLS)
     try_axis("grav_tile", TILES)
     ipl = best["grav_ipl"] or 2
-    try_axis("grav_split", sorted({1, 2, _fill_split(n, ipl)}))
+    try_axis("grav_split", sorted({1, 2, 4, _fill_split(n, ipl)}))
     if precision == sg.SG_FP64:
         try_axis("grav_variant", (1, 2))
     _store(path, _key("grav", precision, n), dict(best=best, ms=best_ms, n=n, tried=rows))

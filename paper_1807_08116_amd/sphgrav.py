@@ -89,6 +89,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsphgrav.so not built: run __graft_entry__.build() "
                           "(or python paper_1807_08116_amd/build.py)")
+    # torch owns device memory and streams: bring its HIP runtime up first so
+    # that the library binds to the runtime (and device list) torch uses.
+    import torch
+    torch.cuda.is_available()
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
     L.sg_workspace_bytes.restype = C.c_size_t
