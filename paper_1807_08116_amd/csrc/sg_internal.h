@@ -20,6 +20,18 @@ enum : uint32_t {
 
 // Grid of smoothing-length levels plus the device status word.  Lives in
 // the workspace; written only by device code during a neighbour build.
+// Workgroups of a launch are dealt to the 8 XCDs of the chip round-robin,
+// and each XCD has its own L2.  Kernels whose neighbouring targets share
+// data (neighbour gathers over slot-ordered particles) remap the block
+// index so that each XCD walks one contiguous range of blocks: a bijection
+// of [0, nb), whatever the hardware's actual placement.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t per = nb / kXcds, rem = nb % kXcds;
+    const int64_t x = b % kXcds, k = b / kXcds;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 struct sg_grid_dev {
     // reduction inputs (order-preserving u64 images of doubles)
     unsigned long long hmin_bits;

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr(const sg_grid_dev* __restrict__ 
     if (err & SGE_SORT_FATAL) return;
     if (FILL && (err & SGE_NNZ)) return;
     const unsigned lane = threadIdx.x & 63;
-    const int64_t s = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (s >= ng) return;                       // uniform per wave
     const double p[3] = {xs[s], ys[s], zs[s]};
     const double hi = hs[s];

@@ -46,7 +46,7 @@ __device__ inline T spline_shape(T xi) {
 __global__ __launch_bounds__(kBlock) void k_density_f64(sg_sph_bufs b, const sg_grid_dev* g,
                                                         int64_t ng, double* __restrict__ rho_out) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (s >= ng) return;
     const sg_prec pi = b.prec[s];
     double acc = pi.m / (kPi * pi.h * pi.h * pi.h);      // self term m_i W(0, h_i)
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_density_f64(sg_sph_bufs b, const sg_
 __global__ __launch_bounds__(kBlock) void k_density_f32(sg_sph_bufs b, const sg_grid_dev* g,
                                                         int64_t ng, double* __restrict__ rho_out) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (s >= ng) return;
     const sg_prec pi = b.prec[s];
     const float hi = (float)pi.h;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_sph_prep(sg_sph_bufs b, const sg_gri
                                                      const double* __restrict__ vz,
                                                      const double* __restrict__ e) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (s >= ng) return;
     const int32_t i = b.perm[s];
     const sg_prec q = b.prec[s];
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f64(sg_sph_bufs b, const s
                                                           double* __restrict__ asz,
                                                           double* __restrict__ dedt) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (s >= ng) return;
     const sg_frec64 a = b.f64[s];
     const double kgrad = -45.0 / (64.0 * kPi);
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const s
                                                           double* __restrict__ asz,
                                                           double* __restrict__ dedt) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (s >= ng) return;
     const sg_frec32 a = b.f32[s];
     const float kgrad = (float)(-45.0 / (64.0 * kPi));
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_cfl(sg_sph_bufs b, const sg_grid_dev
                                                 const double* __restrict__ dedt,
                                                 unsigned long long* __restrict__ out) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     double dt = __builtin_inf();
     if (s < ng && b.nbr_off[s + 1] > b.nbr_off[s]) {
         const sg_frec64 a = b.f64[s];
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_update_h(sg_sph_bufs b, const sg_gri
                                                      int64_t ng, double sigma,
                                                      double* __restrict__ h) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (s >= ng) return;
     h[b.perm[s]] = sigma * cbrt(b.ms[s] / b.rho_s[s]);
 }
