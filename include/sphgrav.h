@@ -184,8 +184,9 @@ sg_status sg_step(sg_ctx *ctx, double dt, uint32_t flags);
  * use_graph != 0, the first step runs eagerly and the steady-state step
  * (step + diagnostics) is captured once into a HIP graph and replayed for
  * the remaining steps (dt is fixed inside the graph; stage timing must be
- * off).  Results are identical to nsteps calls of sg_step.  Waits for the
- * stream before returning. */
+ * off; the context's stream must not be the null stream, which cannot be
+ * captured: SG_EINVAL before any work).  Results are identical to nsteps
+ * calls of sg_step.  Waits for the stream before returning. */
 sg_status sg_run(sg_ctx *ctx, double dt, int64_t nsteps, uint32_t flags, int32_t use_graph,
                  double *d_hist);
 

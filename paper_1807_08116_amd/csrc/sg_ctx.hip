@@ -623,6 +623,8 @@ sg_status sg_run(sg_ctx* c, double dt, int64_t nsteps, uint32_t flags, int32_t u
     if (r != SG_OK) return r;
     if (nsteps < 0) return c->fail(SG_EINVAL, "nsteps must be >= 0");
     if (use_graph && c->prof) return c->fail(SG_ESTATE, "stage timing must be off to capture a graph");
+    if (use_graph && nsteps >= 2 && c->st == nullptr)
+        return c->fail(SG_EINVAL, "graph capture needs a stream other than the null stream");
     double* diag = c->at<double>(c->L.diag_out);
     for (int64_t k = 0; k < nsteps; ++k) {
         if (use_graph && k == 1) break;
@@ -959,6 +961,8 @@ sg_status sg_ensemble_run(sg_ens* e, double dt, int64_t nsteps, uint32_t flags, 
     if (nsteps < 0) return e->fail(SG_EINVAL, "nsteps must be >= 0");
     for (sg_ctx* c : e->c)
         if (use_graph && c->prof) return e->fail(SG_ESTATE, "stage timing must be off to capture");
+    if (use_graph && nsteps >= 2 && e->st == nullptr)
+        return e->fail(SG_EINVAL, "graph capture needs a stream other than the null stream");
     (void)hipGetLastError();
     sg_status r;
     for (int64_t k = 0; k < nsteps; ++k) {

@@ -70,6 +70,18 @@ def test_graph_refuses_while_profiling(sg, c0):
     assert ei.value.code == sg.SG_ESTATE
 
 
+def test_graph_refuses_the_null_stream(sg, c0):
+    eng = sg.Engine(c0, precision=sg.SG_FP64)          # torch's current stream
+    if eng.ctx.stream.cuda_stream != 0:
+        pytest.skip("current stream is not the null stream")
+    x0 = eng.numpy("x").copy()
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.run(1e-3, 3, 0, use_graph=True)
+    assert ei.value.code == sg.SG_EINVAL
+    np.testing.assert_array_equal(eng.numpy("x"), x0)  # refused before any work
+    eng.ctx.run(1e-3, 2, 0, use_graph=False)           # eager steps are fine there
+
+
 @pytest.mark.parametrize("form", ["fp64", "fp32c"])
 def test_checkpoint_resume_bitwise(sg, c0, form):
     # The state (r, v, e, h, m) is all a checkpoint needs: a fresh context
