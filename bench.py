@@ -175,7 +175,8 @@ def main():
     ap.add_argument("--split", type=int, default=0, help="gravity source splits (0 = auto)")
     ap.add_argument("--tile", type=int, default=0, help="gravity sources per LDS tile (0 = auto)")
     ap.add_argument("--variant", type=int, default=0,
-                    help="FP64 gravity kernel: 0 automatic, 1 FP32-seeded rsqrt, 2 FP64-seeded")
+                    help="FP64 gravity kernel: 0 automatic, 1/2 pair differences with FP32-/FP64-"
+                         "seeded rsqrt, 3/4 expanded far field with the same seeds")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()

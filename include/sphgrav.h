@@ -77,10 +77,13 @@ typedef enum {
  *   grav_tile: sources per LDS tile of the gravity kernels (128, 256 or
  *   512; 0 = automatic, 256).  None of the three changes results beyond
  *   summation order.
- * grav_variant: 0 = automatic.  FP64 form: 1 = reciprocal square root
- *   seeded in FP32 and refined in FP64 (needs eps^2 >= 1.2e-38; the
- *   automatic choice), 2 = seeded in FP64 (both refined to FP64 rounding
- *   level).  FP32C form: 1 (the only kernel).
+ * grav_variant: 0 = automatic.  FP64 form: 1 = pair differences, reciprocal
+ *   square root seeded in FP32 and refined in FP64 (needs eps^2 >=
+ *   1.2e-38), 2 = pair differences, seeded in FP64 (both refined to FP64
+ *   rounding level); 3 (FP32 seed, needs eps^2 >= 1.2e-38) and 4 (FP64
+ *   seed) = Morton-ordered particles with the far field expanded about a
+ *   per-workgroup anchor, as the FP32C kernel does, in FP64 (4 is the
+ *   automatic choice).  FP32C form: 1 (the only kernel).
  * cell_scale_log2: side of the neighbour-search cells relative to the
  *   default rule, as a power of two (-1, 0 or +1; 0 = default).  Each gas
  *   particle keeps its level (the first l with L0 * 2^l >= (2 + 2^-9) h_i,
@@ -221,7 +224,7 @@ typedef enum {
     SG_X_NBR_OFF = 5,   /* int64 [N_g+1] CSR row offsets, rows by slot       */
     SG_X_NBR_IDX = 6,   /* int32 [nnz] neighbour slots, ascending per row    */
     SG_X_GRID = 7,      /* sg_grid_info, 1 element                           */
-    SG_X_GORDER = 8     /* int32 [N] gravity target order (SG_FP32C only)    */
+    SG_X_GORDER = 8     /* int32 [N] gravity target order (SG_FP32C, FP64 grav_variant 3/4) */
 } sg_export_what;
 
 /* Host-readable grid description (SG_X_GRID): L0 is the base of the level

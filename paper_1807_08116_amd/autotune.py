@@ -5,8 +5,8 @@ cover every value):
 
 * gravity: targets per lane (a workgroup of 256 lanes owns 256 * ipl
   targets: the "block" of targets), sources per LDS tile (the j-tile: 128,
-  256 or 512), source-range splits and, in the FP64 form, the reciprocal
-  square-root variant;
+  256 or 512), source-range splits and, in the FP64 form, the kernel
+  variant (difference or expanded far field, FP32- or FP64-seeded rsqrt);
 * neighbour grid: the cell size, as a power-of-two scale of the default
   rule (cell_scale_log2 in {-1, 0, 1});
 * ensembles: targets per lane and j-tile of the persistent launch.
@@ -44,7 +44,7 @@ def candidates(precision, n):
     """Every gravity parameter set the search may visit (for validation)."""
     from . import sphgrav as sg
     out = []
-    variants = (1, 2) if precision == sg.SG_FP64 else (0,)
+    variants = (1, 2, 3, 4) if precision == sg.SG_FP64 else (0,)
     for ipl in IPLS:
         for tile in TILES:
             for split in sorted({1, 2, 4, _fill_split(n, ipl)}):
@@ -119,7 +119,7 @@ def tune_gravity(st, precision, reps=2, path=CACHE, verbose=False):
     ipl = best["grav_ipl"] or 2
     try_axis("grav_split", sorted({1, 2, 4, _fill_split(n, ipl)}))
     if precision == sg.SG_FP64:
-        try_axis("grav_variant", (1, 2))
+        try_axis("grav_variant", (1, 2, 3, 4))
     _store(path, _key("grav", precision, n), dict(best=best, ms=best_ms, n=n, tried=rows))
     return best
 

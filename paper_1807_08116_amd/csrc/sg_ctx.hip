@@ -15,12 +15,17 @@ namespace {
 
 thread_local char g_create_msg[256] = "null context";
 
-// grav_variant 0 (automatic) resolved per precision form: FP64 -> 1 (rsqrt
-// seeded in FP32); FP32C has one kernel (1).
-constexpr int kAutoVariantFP64 = 1;
+// grav_variant 0 (automatic) resolved per precision form: FP64 -> 4
+// (expanded far field, FP64-seeded rsqrt: 8 % faster than the difference
+// form at 2M particles); FP32C has one kernel (1).
+constexpr int kAutoVariantFP64 = 4;
 inline int resolved_variant(const sg_params& p) {
     if (p.precision == SG_FP32C) return 1;
     return p.grav_variant != 0 ? p.grav_variant : kAutoVariantFP64;
+}
+// Gravity kernels that work on Morton-ordered copies with per-run boxes.
+inline bool uses_morton(const sg_params& p) {
+    return p.precision == SG_FP32C || resolved_variant(p) >= 3;
 }
 // grav_tile 0 (automatic): 256 sources per LDS tile.
 inline int resolved_tile(const sg_params& p) { return p.grav_tile != 0 ? p.grav_tile : 256; }
@@ -85,9 +90,10 @@ layout make_layout(const sg_params* p, const sg_caps* c) {
     L.gy = take(8 * n);
     L.gz = take(8 * n);
     L.gpot = take(8 * n);
-    L.gorder = take(f32 ? 4 * n : 0);
-    L.morton = take(f32 ? sg_morton_tmp_bytes(n) : 0);
-    L.gsorted = take(f32 ? sg_grav_sorted_bytes(n) : 0);
+    const bool mort = uses_morton(*p);
+    L.gorder = take(mort ? 4 * n : 0);
+    L.morton = take(mort ? sg_morton_tmp_bytes(n) : 0);
+    L.gsorted = take(mort ? sg_grav_sorted_bytes(n) : 0);
     L.part = take(8 * 4 * (size_t)part_cap_elems(n));
     L.vtx = take(8 * n);
     L.vty = take(8 * n);
@@ -113,15 +119,16 @@ bool params_ok(const sg_params* p, const char** why) {
     if (p->grav_ipl != 0 && p->grav_ipl != 1 && p->grav_ipl != 2 && p->grav_ipl != 4)
         return *why = "grav_ipl must be 0, 1, 2 or 4", false;
     if (p->grav_split < 0 || p->grav_split > 64) return *why = "grav_split must be in [0, 64]", false;
-    if (p->precision == SG_FP64 && (p->grav_variant < 0 || p->grav_variant > 2))
-        return *why = "grav_variant must be 0, 1 or 2 in the FP64 form", false;
+    if (p->precision == SG_FP64 && (p->grav_variant < 0 || p->grav_variant > 4))
+        return *why = "grav_variant must be 0..4 in the FP64 form", false;
     if (p->precision == SG_FP32C && p->grav_variant != 0 && p->grav_variant != 1)
         return *why = "grav_variant must be 0 or 1 in the FP32C form", false;
     if (p->grav_tile != 0 && p->grav_tile != 128 && p->grav_tile != 256 && p->grav_tile != 512)
         return *why = "grav_tile must be 0, 128, 256 or 512", false;
     if (p->cell_scale_log2 < -1 || p->cell_scale_log2 > 1)
         return *why = "cell_scale_log2 must be -1, 0 or 1", false;
-    if ((p->precision == SG_FP32C || p->grav_variant != 2) && !(p->eps * p->eps >= 1.2e-38))
+    const int v = resolved_variant(*p);
+    if ((p->precision == SG_FP32C || v == 1 || v == 3) && !(p->eps * p->eps >= 1.2e-38))
         return *why = "FP32 pair arithmetic needs eps^2 in the FP32 normal range", false;
     for (int r : p->reserved)
         if (r != 0) return *why = "reserved fields must be zero", false;
@@ -347,7 +354,7 @@ void grav_args(sg_ctx* c, bool pot, sg_grav_args& a) {
     a.tile = resolved_tile(c->prm);
     a.with_pot = pot ? 1 : 0;
     a.variant = resolved_variant(c->prm);
-    a.order = c->prm.precision == SG_FP32C ? c->at<int32_t>(c->L.gorder) : nullptr;
+    a.order = uses_morton(c->prm) ? c->at<int32_t>(c->L.gorder) : nullptr;
     a.sorted = c->at<void>(c->L.gsorted);
     a.gx = c->at<double>(c->L.gx);
     a.gy = c->at<double>(c->L.gy);
@@ -356,10 +363,10 @@ void grav_args(sg_ctx* c, bool pot, sg_grav_args& a) {
     a.part = c->at<double>(c->L.part);
 }
 
-// FP32C: Morton order, sorted copies and 64-particle boxes at the current
-// positions (nothing to do in the FP64 form).
+// Morton order, sorted copies and 64-particle boxes at the current
+// positions (FP32C and the FP64 expanded-far-field kernels only).
 sg_status grav_prep(sg_ctx* c, const sg_grav_args& a) {
-    if (c->prm.precision != SG_FP32C) return SG_OK;
+    if (!uses_morton(c->prm)) return SG_OK;
     c->begin(SG_ST_GRAV_PREP);
     sg_launch_morton_order(c->s.x, c->s.y, c->s.z, c->n, c->grid(), const_cast<int32_t*>(a.order),
                            c->at<void>(c->L.morton), c->st);
@@ -720,7 +727,7 @@ sg_status sg_export(sg_ctx* c, int32_t what, void* dst, int64_t cap_bytes, int64
         case SG_X_NBR_OFF: src = c->at<void>(c->L.nbr_off); n = ng + 1; esz = 8; break;
         case SG_X_NBR_IDX: src = c->at<void>(c->L.nbr_idx); n = g.nnz; esz = 4; break;
         case SG_X_GORDER:
-            if (c->prm.precision != SG_FP32C) return c->fail(SG_EINVAL, "no gravity order in FP64 form");
+            if (!uses_morton(c->prm)) return c->fail(SG_EINVAL, "no gravity order for this kernel");
             src = c->at<void>(c->L.gorder); n = c->n; esz = 4; break;
         case SG_X_GRID: {
             if (cap_bytes < (int64_t)sizeof(sg_grid_info)) return c->fail(SG_ECAPACITY, "buffer too small");

@@ -396,6 +396,170 @@ __global__ __launch_bounds__(kBlock) void k_grav_f32c_ens(const sg_ens_sys* __re
     }
 }
 
+// FP64 form with the expanded far field (grav_variant 3, 4).  Same
+// structure as the FP32C kernel: Morton-ordered targets and sources, an
+// anchor P at the centre of the workgroup's target box, near-field source
+// runs (box within D/8) in the difference form, far-field runs as
+// r^2 + eps^2 = (|x_i|^2 + eps^2) + |x_j|^2 - 2 x_i . x_j and
+// sum s m (x_j - x_i) = sum s (m x_j) - x_i sum s m, all in FP64 (no
+// compensation needed).  Outside the near field |x| <= 5 r, so both
+// rewritings cost a few units of 2^-53 per pair.  Per far pair: 1 add,
+// 8 FMAs, 2 multiplies and the refined reciprocal square root, against
+// 3 subtractions, 6 FMAs, 4 multiplies and 1 add in the difference form.
+template <int TILE>
+struct f64x_lds {
+    d4 b[2][TILE];             // (-2 x, -2 y, -2 z, |x|^2), anchor-relative
+    d4 w[2][TILE];             // (m x, m y, m z, m)
+    int near[2][TILE / kSub];
+};
+
+template <int IPL, int TILE, bool POT, bool SEED32>
+__global__ __launch_bounds__(kBlock) void k_grav_f64x(
+    const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ zs,
+    const double* __restrict__ ms, const box6* __restrict__ sbox, const int32_t* __restrict__ order,
+    int64_t n, int64_t jchunk, double eps2, double G, double inv_eps, int final_out,
+    double* __restrict__ ox, double* __restrict__ oy, double* __restrict__ oz,
+    double* __restrict__ op, int64_t ostride) {
+    constexpr int kPer = (TILE + kBlock - 1) / kBlock;   // sources staged per lane
+    __shared__ f64x_lds<TILE> L;
+    const int tid = threadIdx.x;
+    const int64_t ib = (int64_t)blockIdx.x * (kBlock * IPL);
+    const int64_t j0 = (int64_t)blockIdx.y * jchunk;
+    int64_t j1 = j0 + jchunk;
+    if (j1 > n) j1 = n;
+    box6 bb;
+    {
+        const int64_t s0 = ib / kSub;
+        int64_t s1 = (ib + kBlock * IPL + kSub - 1) / kSub;
+        const int64_t nsub = (n + kSub - 1) / kSub;
+        if (s1 > nsub) s1 = nsub;
+        bb = sbox[s0];
+        for (int64_t q = s0 + 1; q < s1; ++q) {
+            const box6 o = sbox[q];
+            for (int d = 0; d < 3; ++d) {
+                bb.lo[d] = o.lo[d] < bb.lo[d] ? o.lo[d] : bb.lo[d];
+                bb.hi[d] = o.hi[d] > bb.hi[d] ? o.hi[d] : bb.hi[d];
+            }
+        }
+    }
+    const double Px = 0.5 * (bb.lo[0] + bb.hi[0]);
+    const double Py = 0.5 * (bb.lo[1] + bb.hi[1]);
+    const double Pz = 0.5 * (bb.lo[2] + bb.hi[2]);
+    double diag2 = 0.0;
+    for (int d = 0; d < 3; ++d) diag2 += (bb.hi[d] - bb.lo[d]) * (bb.hi[d] - bb.lo[d]);
+    const double near2 = kNearFrac * kNearFrac * diag2;
+
+    double xi[IPL], yi[IPL], zi[IPL], ck[IPL];
+    double fx[IPL], fy[IPL], fz[IPL], f1[IPL], fp[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        int64_t i = ib + k * kBlock + tid;
+        if (i >= n) i = ib;
+        xi[k] = xs[i] - Px;
+        yi[k] = ys[i] - Py;
+        zi[k] = zs[i] - Pz;
+        ck[k] = __builtin_fma(xi[k], xi[k], __builtin_fma(yi[k], yi[k], __builtin_fma(zi[k], zi[k], eps2)));
+        fx[k] = fy[k] = fz[k] = f1[k] = fp[k] = 0.0;
+    }
+    // sources past j1 stage as massless points at the anchor
+    auto stage = [&](int buf, int64_t jt) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int jl = u * kBlock + tid;
+            if (jl >= TILE) break;
+            const int64_t j = jt + jl;
+            d4 b{0, 0, 0, 0}, w{0, 0, 0, 0};
+            if (j < j1) {
+                const double dx = xs[j] - Px, dy = ys[j] - Py, dz = zs[j] - Pz, m = ms[j];
+                b = d4{-2.0 * dx, -2.0 * dy, -2.0 * dz,
+                       __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz))};
+                w = d4{m * dx, m * dy, m * dz, m};
+            }
+            L.b[buf][jl] = b;
+            L.w[buf][jl] = w;
+        }
+        if (tid < TILE / kSub) {
+            const int64_t q = jt / kSub + tid;
+            int nr = 0;
+            if (jt + (int64_t)tid * kSub < j1) nr = box_gap2(bb, sbox[q]) < near2;
+            L.near[buf][tid] = nr;
+        }
+    };
+
+    stage(0, j0);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t jt = j0; jt < j1; jt += TILE) {
+        const bool more = jt + TILE < j1;
+        for (int sb = 0; sb < TILE / kSub; ++sb) {
+            if (L.near[cur][sb]) {
+#pragma unroll 2
+                for (int jj = sb * kSub; jj < (sb + 1) * kSub; ++jj) {
+                    const d4 b = L.b[cur][jj];
+                    const double m = L.w[cur][jj].w;
+                    const double qx = -0.5 * b.x, qy = -0.5 * b.y, qz = -0.5 * b.z;   // exact
+#pragma unroll
+                    for (int k = 0; k < IPL; ++k) {
+                        const double dx = qx - xi[k], dy = qy - yi[k], dz = qz - zi[k];
+                        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+                        const double rinv = rsqrt_f64<SEED32>(r2);
+                        const double mr = m * rinv;
+                        const double sv = mr * (rinv * rinv);
+                        fx[k] = __builtin_fma(sv, dx, fx[k]);
+                        fy[k] = __builtin_fma(sv, dy, fy[k]);
+                        fz[k] = __builtin_fma(sv, dz, fz[k]);
+                        if (POT) fp[k] += mr;
+                    }
+                }
+            } else {
+#pragma unroll 4
+                for (int jj = sb * kSub; jj < (sb + 1) * kSub; ++jj) {
+                    const d4 b = L.b[cur][jj];
+                    const d4 w = L.w[cur][jj];
+#pragma unroll
+                    for (int k = 0; k < IPL; ++k) {
+                        const double r2 = __builtin_fma(xi[k], b.x, __builtin_fma(yi[k], b.y,
+                                          __builtin_fma(zi[k], b.z, b.w + ck[k])));
+                        const double rinv = rsqrt_f64<SEED32>(r2);
+                        const double sv = (rinv * rinv) * rinv;
+                        fx[k] = __builtin_fma(sv, w.x, fx[k]);
+                        fy[k] = __builtin_fma(sv, w.y, fy[k]);
+                        fz[k] = __builtin_fma(sv, w.z, fz[k]);
+                        f1[k] = __builtin_fma(sv, w.w, f1[k]);
+                        if (POT) fp[k] = __builtin_fma(rinv, w.w, fp[k]);
+                    }
+                }
+            }
+        }
+        __syncthreads();                       // everyone is done with tile `cur`
+        if (more) stage(cur ^ 1, jt + TILE);
+        __syncthreads();
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int64_t i = ib + k * kBlock + tid;
+        if (i >= n) continue;
+        const int32_t t = order[i];
+        if ((uint64_t)t >= (uint64_t)n) continue;
+        const double gx = fx[k] - xi[k] * f1[k];
+        const double gy = fy[k] - yi[k] * f1[k];
+        const double gz = fz[k] - zi[k] * f1[k];
+        if (final_out) {
+            ox[t] = G * gx;
+            oy[t] = G * gy;
+            oz[t] = G * gz;
+            if (POT) op[t] = -G * (fp[k] - ms[i] * inv_eps);
+        } else {
+            const int64_t o = (int64_t)blockIdx.y * ostride + t;
+            ox[o] = gx;
+            oy[o] = gy;
+            oz[o] = gz;
+            if (POT) op[o] = fp[k];
+        }
+    }
+}
+
 __global__ void k_counter_reset(int32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
@@ -469,7 +633,16 @@ void launch_t(const sg_grav_args& a, dim3 grid, int64_t jchunk, int final_out, d
                            a.zs, a.ms, (const box6*)a.sbox, a.order, a.n, jchunk,
                            (float)(a.eps * a.eps), a.G, inv_eps, final_out, ox, oy, oz, op,
                            ostride);
-    else if (a.variant == 2)
+    else if (a.variant == 3 || a.variant == 4) {
+        if (a.variant == 3)
+            hipLaunchKernelGGL((k_grav_f64x<IPL, TILE, POT, true>), grid, dim3(kBlock), 0, st,
+                               a.xs, a.ys, a.zs, a.ms, (const box6*)a.sbox, a.order, a.n, jchunk,
+                               a.eps * a.eps, a.G, inv_eps, final_out, ox, oy, oz, op, ostride);
+        else
+            hipLaunchKernelGGL((k_grav_f64x<IPL, TILE, POT, false>), grid, dim3(kBlock), 0, st,
+                               a.xs, a.ys, a.zs, a.ms, (const box6*)a.sbox, a.order, a.n, jchunk,
+                               a.eps * a.eps, a.G, inv_eps, final_out, ox, oy, oz, op, ostride);
+    } else if (a.variant == 2)
         hipLaunchKernelGGL((k_grav_f64<IPL, TILE, POT, false>), grid, dim3(kBlock), 0, st, a.x,
                            a.y, a.z, a.m, a.n, jchunk, a.eps * a.eps, a.G, inv_eps, final_out, ox,
                            oy, oz, op, ostride);
@@ -603,10 +776,11 @@ int sg_launch_gravity(const sg_grav_args& a_in, hipStream_t st) {
     if (!a_in.x || !a_in.y || !a_in.z || !a_in.m || !a_in.gx || !a_in.gy || !a_in.gz ||
         !a_in.gpot || !a_in.part || a_in.n < 1)
         return -1;
-    if (a_in.precision == SG_FP32C && (!a_in.order || !a_in.sorted)) return -1;
+    const bool morton = a_in.precision == SG_FP32C || a_in.variant >= 3;
+    if (morton && (!a_in.order || !a_in.sorted)) return -1;
     if (a_in.tile != 128 && a_in.tile != 256 && a_in.tile != 512) return -1;
     sg_grav_args a = a_in;
-    if (a.precision == SG_FP32C) sorted_views(a);
+    if (morton) sorted_views(a);
     const int ipl = a.ipl == 1 || a.ipl == 2 ? a.ipl : 4;
     const int64_t per = (int64_t)kBlock * ipl;
     const int64_t iblocks = (a.n + per - 1) / per;

@@ -152,10 +152,11 @@ struct sg_grav_args {
     double G, eps;
     int precision, ipl, split, with_pot;
     int tile;                           // sources per LDS tile: 128, 256 or 512
-    int variant;                        // resolved: FP64 1 = FP32-seeded rsqrt, 2 = FP64-seeded;
-                                        // FP32C 1 (the only one)
-    const int32_t* order;               // FP32C: Morton order of the particles, else null
-    void* sorted;                       // FP32C: scratch of sg_grav_sorted_bytes(n)
+    int variant;                        // resolved: FP64 1/2 = difference form with FP32-/FP64-
+                                        // seeded rsqrt, 3/4 = expanded far field (Morton order,
+                                        // same seeds); FP32C 1 (the only one)
+    const int32_t* order;               // FP32C, FP64 3/4: Morton order of the particles
+    void* sorted;                       // FP32C, FP64 3/4: scratch of sg_grav_sorted_bytes(n)
     const double *xs, *ys, *zs, *ms;    // (set by the launcher) sorted copies
     const void* sbox;                   // (set by the launcher) sub-tile boxes
     double *gx, *gy, *gz, *gpot;        // outputs [n], particle order

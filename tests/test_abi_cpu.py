@@ -39,13 +39,15 @@ def test_workspace_validation(sg):
     assert sg.workspace_bytes(good, caps) > 0
     for bad in (dict(eps=0.0), dict(eps=-1.0), dict(gamma=1.0), dict(alpha=-1.0),
                 dict(eta=0.0), dict(precision=7), dict(grav_ipl=3), dict(grav_split=65),
-                dict(G=float("nan")), dict(grav_variant=3), dict(eps=1e-20),
+                dict(G=float("nan")), dict(grav_variant=5), dict(grav_variant=3, eps=1e-20),
+                dict(grav_variant=1, eps=1e-20),
                 dict(precision=1, grav_variant=2), dict(precision=1, eps=1e-20),
                 dict(grav_tile=64), dict(grav_tile=1024), dict(cell_scale_log2=2),
                 dict(cell_scale_log2=-2)):
         assert sg.workspace_bytes(sg.make_params(**bad), caps) == 0, bad
     for ok in (dict(grav_tile=128), dict(grav_tile=512), dict(cell_scale_log2=-1),
-               dict(cell_scale_log2=1), dict(grav_variant=2, eps=1e-20)):
+               dict(cell_scale_log2=1), dict(grav_variant=2, eps=1e-20),
+               dict(grav_variant=3), dict(grav_variant=4, eps=1e-20), dict(eps=1e-20)):
         assert sg.workspace_bytes(sg.make_params(**ok), caps) > 0, ok
     p = sg.make_params()
     p.reserved[1] = 1

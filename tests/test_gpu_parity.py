@@ -145,7 +145,8 @@ def test_c0_forces(sg, orc, c0, c0_ref, precision):
 # has one kernel and takes the same shapes with variant 0
 @pytest.mark.parametrize("ipl,split,variant,tile", [
     (1, 1, 0, 0), (2, 3, 1, 128), (4, 1, 2, 512), (4, 1, 1, 256), (1, 64, 2, 128),
-    (4, 7, 1, 512), (0, 0, 2, 0), (0, 5, 2, 512), (2, 1, 1, 512), (2, 2, 0, 128)])
+    (4, 7, 1, 512), (0, 0, 2, 0), (0, 5, 2, 512), (2, 1, 1, 512), (2, 2, 0, 128),
+    (4, 1, 3, 256), (2, 3, 4, 128), (1, 64, 3, 512), (0, 0, 4, 0), (4, 2, 3, 512)])
 def test_gravity_launch_shapes(sg, orc, c0, c0_ref, ipl, split, variant, tile):
     ref, *_ = c0_ref
     for p in (sg.SG_FP64, sg.SG_FP32C):
