@@ -454,3 +454,16 @@ def test_h_update_lattice(orc):
     c = (n // 2) * n * n + (n // 2) * n + n // 2
     assert abs(hn[c] / (1.25 * d) - 1) < 1e-3
     assert np.all(orc.update_h(m, rho, 2.5) == 2 * hn)          # linear in sigma
+
+
+@pytest.mark.parametrize("h", [0.5, 2.0])
+def test_kernel_values_golden(orc, h):
+    # Hand-evaluated values of the printed kernels (tests/golden/kernel_values.txt).
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "kernel_values.txt")
+    rows = np.loadtxt(path, comments="#")
+    scale = PI * h ** 3
+    for xi, w, wp, dwp in rows:
+        assert abs(orc.W(xi * h, h) * scale - w) < 1e-14
+        assert abs(orc.Wp(xi * h, h) * scale - wp) < 1e-14
+        assert abs(orc.dWp_dxi(xi * h, h) * scale - dwp) < 1e-14
