@@ -149,17 +149,37 @@ def cpu_baseline(st, sample, prm):
     ref[gas, 1] += asy[sample[gas]]
     ref[gas, 2] += asz[sample[gas]]
     step_s = t_nbr + t_dens + 2 * t_sph + t_grav * n / len(sample)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.get_threads()
+    # one thread: density, forces and gravity of 256 of the targets (the
+    # k-d tree neighbour search keeps its all-core time)
+    oracle.set_threads(1)
     try:
-        cores = min(cores, len(os.sched_getaffinity(0)))
-    except AttributeError:
-        pass
+        t = time.perf_counter()
+        rho1 = oracle.density(x, y, z, st["m"][:ng], st["h"], *nb)
+        t1_dens = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.sph_force(x, y, z, st["vx"][:ng], st["vy"][:ng], st["vz"][:ng], st["m"][:ng],
+                         st["h"], rho1, st["e"], prm["gamma"], prm["alpha"], prm["beta"],
+                         prm["eta"], *nb)
+        t1_sph = time.perf_counter() - t
+        s1 = sample[:: max(1, len(sample) // 256)]
+        t = time.perf_counter()
+        oracle.gravity(st["x"], st["y"], st["z"], st["m"], prm["G"], prm["eps"], s1)
+        t1_grav = time.perf_counter() - t
+    finally:
+        oracle.set_threads(cores)
+    step1_s = t_nbr + t1_dens + 2 * t1_sph + t1_grav * n / len(s1)
     return ref, {
         "value": 1.0 / step_s, "unit": "force-steps/s", "cores": cores, "kind": "oracle",
         "sample": ("gravity of %d seeded targets over all %d sources (x%.0f to a step) + whole "
                    "SPH part (neighbours %.1fs, density %.1fs, forces %.1fs x2); gravity %.1fs"
                    % (len(sample), n, n / len(sample), t_nbr, t_dens, t_sph, t_grav)),
         "extrapolated": True,
+        "single_core": {"value": 1.0 / step1_s, "unit": "force-steps/s", "cores": 1,
+                        "sample": ("one thread: gravity of %d of the targets (x%.0f) + "
+                                   "density %.1fs + forces %.1fs x2; gravity %.1fs; the "
+                                   "neighbour search's all-core time (%.1fs) is included"
+                                   % (len(s1), n / len(s1), t1_dens, t1_sph, t1_grav, t_nbr))},
     }
 
 
@@ -263,6 +283,13 @@ def main():
         }
     if "fp64" in res and "fp32c" in res:
         out["fp32c_vs_fp64_speedup"] = res["fp64"]["sec"] / res["fp32c"]["sec"]
+    if "fp64" in res and head != "fp64":
+        ms64, n64 = res["fp64"]["prof"]["grav"]
+        s64 = ms64 / 1e3 / max(n64, 1)
+        a64 = FLOPS_PER_PAIR * float(n) * float(n) / s64 / 1e12
+        out["roofline_fp64"] = {"bound": "alu", "achieved": a64, "peak": PEAK["fp64"],
+                                "unit": "TFLOP/s", "frac": a64 / PEAK["fp64"],
+                                "kernel": "gravity pair kernel (fp64), %.1f ms/launch" % (1e3 * s64)}
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

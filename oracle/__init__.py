@@ -125,6 +125,9 @@ def lib():
         L.or_update_h.restype = None
         L.or_update_h.argtypes = [_i64, _dbl, _D, _D, _D]
         L.or_max_levels.restype = C.c_int
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_get_threads.restype = C.c_int
         L.or_grid_size.restype = C.c_size_t
         assert L.or_max_levels() == MAX_LEVELS
         assert L.or_grid_size() == C.sizeof(Grid), "Grid struct layout mismatch"
@@ -160,6 +163,15 @@ def pred(pi, hi, pj, hj):
 # --------------------------------------------------------------------------
 # Grid, keys, counting sort
 # --------------------------------------------------------------------------
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().or_get_threads())
+
 
 def grid(x, y, z, h, cell_scale_log2=0):
     g = Grid()
@@ -258,11 +270,11 @@ def nbrs_kdtree(x, y, z, h, workers=None):
     return off, idx
 
 
-def nbrs(x, y, z, h):
+def nbrs(x, y, z, h, workers=None):
     """Exact id-space neighbour rows; brute force for small inputs."""
     if len(x) <= 20000:
         return nbrs_brute(x, y, z, h)
-    return nbrs_kdtree(x, y, z, h)
+    return nbrs_kdtree(x, y, z, h, workers)
 
 
 def rows_to_slots(perm, off, idx):

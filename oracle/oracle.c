@@ -673,4 +673,14 @@ void or_update_h(int64_t ng, double sigma, const double *m, const double *rho, d
 }
 
 int or_max_levels(void) { return OR_MAX_LEVELS; }
+
+/* Threads of the OpenMP loops (timing on one core or on all of them). */
+#ifdef _OPENMP
+#include <omp.h>
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }
+#else
+void or_set_threads(int n) { (void)n; }
+int or_get_threads(void) { return 1; }
+#endif
 size_t or_grid_size(void) { return sizeof(or_grid_t); }
