@@ -45,7 +45,7 @@ struct layout {
     size_t count, cursor, hmax, off;
     size_t scan;
     size_t xs, ys, zs, hs, ms, rho_s, prec, f64, f32;
-    size_t ncnt, nbr_off, nbr_idx;
+    size_t ncnt, nbr_off, nbr_idx, nbr_slots;
     size_t asx, asy, asz;
     size_t gx, gy, gz, gpot;
     size_t gorder, morton, gsorted;
@@ -83,6 +83,7 @@ layout make_layout(const sg_params* p, const sg_caps* c) {
     L.ncnt = take(4 * ng);
     L.nbr_off = take(8 * (ng + 1));
     L.nbr_idx = take(4 * Z);
+    L.nbr_slots = take(sg_nbr_slot_bytes(ng));
     L.asx = take(8 * ng);
     L.asy = take(8 * ng);
     L.asz = take(8 * ng);
@@ -315,11 +316,12 @@ sg_status do_build(sg_ctx* c) {
     c->begin(SG_ST_NBR);
     int32_t* ncnt = c->at<int32_t>(c->L.ncnt);
     int64_t* nbr_off = c->at<int64_t>(c->L.nbr_off);
-    sg_launch_nbr_count(g, ng, b.xs, b.ys, b.zs, b.hs, off, ncnt, st);
+    int32_t* slots = c->at<int32_t>(c->L.nbr_slots);
+    sg_launch_nbr_search(g, ng, b.xs, b.ys, b.zs, b.hs, off, ncnt, slots, st);
     sg_launch_scan(ncnt, nbr_off, ng, nullptr, ng, scan, st);
     sg_launch_nbr_check(g, nbr_off, ng, c->caps.nnz_cap, st);
-    sg_launch_nbr_fill(g, ng, b.xs, b.ys, b.zs, b.hs, off, nbr_off, c->at<int32_t>(c->L.nbr_idx),
-                       c->caps.nnz_cap, st);
+    sg_launch_nbr_compact(g, ng, b.xs, b.ys, b.zs, b.hs, off, ncnt, slots, nbr_off,
+                          c->at<int32_t>(c->L.nbr_idx), st);
     c->end();
     sg_status r = c->check_launch("neighbour build");
     if (r != SG_OK) return r;

@@ -96,15 +96,18 @@ void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
                           double* ms, sg_prec* prec, hipStream_t st);
 
 // Neighbour lists.
-void sg_launch_nbr_count(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
-                         const double* zs, const double* hs, const int64_t* off, int32_t* cnt,
-                         hipStream_t st);
+// Neighbour search: per-target slots of fixed length (sg_nbr_slot_bytes),
+// counts, then (after the scan and the capacity check) the copy into CSR.
+size_t sg_nbr_slot_bytes(int64_t ng);
+void sg_launch_nbr_search(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
+                          const double* zs, const double* hs, const int64_t* off, int32_t* cnt,
+                          int32_t* slots, hipStream_t st);
 void sg_launch_nbr_check(sg_grid_dev* g, const int64_t* nbr_off, int64_t ng, int64_t nnz_cap,
                          hipStream_t st);
-void sg_launch_nbr_fill(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
-                        const double* zs, const double* hs, const int64_t* off,
-                        const int64_t* nbr_off, int32_t* nbr_idx, int64_t nnz_cap,
-                        hipStream_t st);
+void sg_launch_nbr_compact(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
+                           const double* zs, const double* hs, const int64_t* off,
+                           const int32_t* cnt, const int32_t* slots, const int64_t* nbr_off,
+                           int32_t* nbr_idx, hipStream_t st);
 
 // SPH.  Per-particle data in sorted-slot order is packed into one record
 // per particle, so a neighbour gather touches one or two cache lines.
