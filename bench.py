@@ -268,6 +268,8 @@ def main():
         "cpu_baseline": cpu,
         "accel_err_vs_oracle": errs,
         "pairs_per_s": float(n) * n / grav_s,
+        "software": {"library": sg.lib().sg_version().decode(),
+                     "hip": getattr(torch.version, "hip", None), "torch": torch.__version__},
     }
     for form in res:
         pr = res[form]["prof"]

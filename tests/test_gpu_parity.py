@@ -189,16 +189,22 @@ def test_diagnostics(sg, orc, c0, c0_ref):
     del torch
 
 
-def test_determinism(sg, c0):
+@pytest.mark.parametrize("form", ["fp32c", "fp64"])
+def test_determinism(sg, c0, form):
+    # no float atomics, stable ranks, fixed-order reductions: three fresh
+    # contexts give bit-identical lists, states and forces
+    p = sg.SG_FP32C if form == "fp32c" else sg.SG_FP64
     outs = []
-    for _ in range(2):
-        eng = sg.Engine(c0, precision=sg.SG_FP32C)
+    for _ in range(3):
+        eng = sg.Engine(c0, precision=p)
         full_eval(eng, sg)
         eng.ctx.step(1e-3, sg.SG_POT)
         eng.ctx.sync()
-        outs.append([eng.numpy(f).copy() for f in ("x", "vx", "ax", "rho", "dedt", "pot")])
-    for a, b in zip(*outs):
-        np.testing.assert_array_equal(a, b)
+        outs.append([eng.numpy(f).copy() for f in ("x", "vx", "ax", "rho", "dedt", "pot")] +
+                    [eng.ctx.export(sg.SG_X_NBR_IDX), eng.ctx.export(sg.SG_X_PERM)])
+    for run in outs[1:]:
+        for a, b in zip(outs[0], run):
+            np.testing.assert_array_equal(a, b)
 
 
 # ------------------------------------------------------------ edge cases --
