@@ -102,7 +102,7 @@ def test_fullsize_parity(sg, big, form):
     assert e_rho < tol
     assert e_tot < tol
     assert e_pot < tol
-    assert e_de < (tol if form == "fp64" else 1e-5)
+    assert e_de < tol
 
 
 def test_fullsize_step_conserves_momentum(sg, big):

@@ -137,7 +137,7 @@ def test_c0_forces(sg, orc, c0, c0_ref, precision):
     e_de = nrm_err(eng.numpy("dedt")[:ng], ref["dedt"])
     e_pot = nrm_err(eng.numpy("pot"), ref["pot"])
     print(precision, "rho", e_rho, "acc", e_acc, "dedt", e_de, "pot", e_pot)
-    assert e_rho < tol and e_acc < tol and e_de < (tol if p == sg.SG_FP64 else 1e-5)
+    assert e_rho < tol and e_acc < tol and e_de < tol
     assert e_pot < tol
 
 
@@ -237,7 +237,9 @@ def test_edge_sizes(sg, orc, ng, nh, dup):
     assert nrm_err(gpu_accel(eng), oracle_accel(orc, st, ref)) < FP64_TOL
     eng32 = sg.Engine(st, precision=sg.SG_FP32C)
     full_eval(eng32, sg)
-    assert nrm_err(gpu_accel(eng32), oracle_accel(orc, st, ref)) < 1e-5
+    e32 = nrm_err(gpu_accel(eng32), oracle_accel(orc, st, ref))
+    print("edge", ng, nh, dup, "fp32c acc", e32)
+    assert e32 < FP32C_TOL
 
 
 def test_capacity_overflow_and_retry(sg, orc, c0, c0_ref):
