@@ -75,8 +75,8 @@ typedef enum {
  *   0 = automatic); a workgroup of 256 lanes owns 256 * grav_ipl targets.
  *   grav_split: number of source-range splits (>= 1; 0 = automatic).
  *   grav_tile: sources per LDS tile of the gravity kernels (128, 256 or
- *   512; 0 = automatic, 256).  None of the three changes results beyond
- *   summation order.
+ *   512; 0 = automatic: 256 for SG_FP32C, 512 for SG_FP64).  None of the
+ *   three changes results beyond summation order.
  * grav_variant: 0 = automatic.  FP64 form: 1 = pair differences, reciprocal
  *   square root seeded in FP32 and refined in FP64 (needs eps^2 >=
  *   1.2e-38), 2 = pair differences, seeded in FP64 (both refined to FP64

@@ -27,8 +27,13 @@ inline int resolved_variant(const sg_params& p) {
 inline bool uses_morton(const sg_params& p) {
     return p.precision == SG_FP32C || resolved_variant(p) >= 3;
 }
-// grav_tile 0 (automatic): 256 sources per LDS tile.
-inline int resolved_tile(const sg_params& p) { return p.grav_tile != 0 ? p.grav_tile : 256; }
+// grav_tile 0 (automatic): 256 sources per LDS tile for FP32C, 512 for FP64
+// (measured at 2M particles: FP64 2569 ms with 512 against 2640 with 256;
+// FP32C best at 256).
+inline int resolved_tile(const sg_params& p) {
+    if (p.grav_tile != 0) return p.grav_tile;
+    return p.precision == SG_FP64 ? 512 : 256;
+}
 
 constexpr size_t kAlign = 256;
 inline size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
