@@ -67,8 +67,8 @@ def big(request, orc):
     return request.param, st, sample, _oracle_ref(orc, st, sample)
 
 
-def _evaluate(sg, st, precision):
-    eng = sg.Engine(st, precision=precision)
+def _evaluate(sg, st, precision, **kw):
+    eng = sg.Engine(st, precision=precision, **kw)
     eng.build_neighbors()
     eng.ctx.compute_density()
     eng.ctx.compute_accel(sg.SG_SPH | sg.SG_GRAV | sg.SG_POT)
@@ -76,13 +76,15 @@ def _evaluate(sg, st, precision):
     return eng
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+# fp64: the default FP64 kernel (expanded far field on Morton order);
+# fp64d: the FP64 difference form (grav_variant 1)
+@pytest.mark.parametrize("form", ["fp64", "fp64d", "fp32c"])
 def test_fullsize_parity(sg, big, form):
     name, st, sample, ref = big
-    p = sg.SG_FP64 if form == "fp64" else sg.SG_FP32C
-    tol = FP64_TOL if form == "fp64" else FP32C_TOL
+    p = sg.SG_FP32C if form == "fp32c" else sg.SG_FP64
+    tol = FP32C_TOL if form == "fp32c" else FP64_TOL
     ng = st["ng"]
-    eng = _evaluate(sg, st, p)
+    eng = _evaluate(sg, st, p, **({"grav_variant": 1} if form == "fp64d" else {}))
     ctx = eng.ctx
     s = ref["sort"]
     np.testing.assert_array_equal(ctx.export(sg.SG_X_KEYS), s["key"])
