@@ -796,6 +796,10 @@ sg_status sg_sync(sg_ctx* c, int64_t need[2]) {
 struct sg_ens {
     std::vector<sg_ctx*> c;
     hipStream_t st;
+    // side streams (default priority) that run the systems' own launches
+    // side by side, forked from and joined back into st with events
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
     sg_ens_sys* d_sys;
     sg_ens_task* d_tasks;
     int32_t* d_counter;
@@ -807,8 +811,14 @@ struct sg_ens {
         snprintf(msg, sizeof(msg), "%s", m);
         return code;
     }
+    ~sg_ens() {
+        if (st) (void)hipStreamSynchronize(st);
+        for (hipStream_t x : side) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    }
 };
 
+extern "C++" {  // the helpers below are templates
 namespace {
 
 size_t ens_layout(int32_t nsys, int64_t ntasks, size_t* o_tasks, size_t* o_counter) {
@@ -820,13 +830,53 @@ size_t ens_layout(int32_t nsys, int64_t ntasks, size_t* o_tasks, size_t* o_count
     return o;
 }
 
+// Run fn(c) for every system: system k on side stream k mod K, all side
+// streams forked from the shared stream and joined back into it (also while
+// the shared stream is being captured into a graph: the side streams then
+// join the capture).  Without side streams, in order on the shared stream.
+template <typename F>
+sg_status ens_each(sg_ens* e, F&& fn) {
+    const int K = (int)e->side.size();
+    if (K == 0) {
+        for (sg_ctx* c : e->c) {
+            const sg_status r = fn(c);
+            if (r != SG_OK) return e->fail(r, c->msg);
+        }
+        return SG_OK;
+    }
+    if (hipEventRecord(e->ev[0], e->st) != hipSuccess) return e->fail(SG_EDEVICE, "fork: event record failed");
+    for (int i = 0; i < K; ++i)
+        if (hipStreamWaitEvent(e->side[i], e->ev[0], 0) != hipSuccess)
+            return e->fail(SG_EDEVICE, "fork: stream wait failed");
+    sg_status rc = SG_OK;
+    char why[256] = "";
+    for (size_t k = 0; k < e->c.size() && rc == SG_OK; ++k) {
+        sg_ctx* c = e->c[k];
+        hipStream_t own = c->st;
+        c->st = e->side[k % K];
+        rc = fn(c);
+        c->st = own;
+        if (rc != SG_OK) snprintf(why, sizeof(why), "%s", c->msg);
+    }
+    // join every side stream (also after an error, so a capture stays whole)
+    for (int i = 0; i < K; ++i) {
+        const bool ok = hipEventRecord(e->ev[i + 1], e->side[i]) == hipSuccess &&
+                        hipStreamWaitEvent(e->st, e->ev[i + 1], 0) == hipSuccess;
+        if (!ok && rc == SG_OK) {
+            rc = SG_EDEVICE;
+            snprintf(why, sizeof(why), "join: event record or stream wait failed");
+        }
+    }
+    return rc == SG_OK ? SG_OK : e->fail(rc, why);
+}
+
 sg_status ens_gravity(sg_ens* e, bool pot) {
-    for (sg_ctx* c : e->c) {
+    sg_status r = ens_each(e, [&](sg_ctx* c) {
         sg_grav_args a;
         grav_args(c, pot, a);
-        sg_status r = grav_prep(c, a);
-        if (r != SG_OK) return e->fail(r, c->msg);
-    }
+        return grav_prep(c, a);
+    });
+    if (r != SG_OK) return r;
     sg_ctx* c0 = e->c[0];
     c0->begin(SG_ST_GRAV);
     sg_launch_grav_ensemble(e->d_sys, e->d_tasks, e->ntasks, e->d_counter, pot ? 1 : 0, e->eps,
@@ -854,24 +904,27 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
         need_grav |= !c->have_grav || (pot && !c->have_pot);
     }
     if (need_grav && (r = ens_gravity(e, pot)) != SG_OK) return r;
-    for (sg_ctx* c : e->c) {
-        if ((r = do_sph(c)) != SG_OK) return e->fail(r, c->msg);
+    r = ens_each(e, [&](sg_ctx* c) {
+        sg_status q;
+        if ((q = do_sph(c)) != SG_OK) return q;
         do_combine(c);
-        if ((r = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return e->fail(r, c->msg);
-        if ((r = do_build(c)) != SG_OK) return e->fail(r, c->msg);
-        if ((r = do_density(c)) != SG_OK) return e->fail(r, c->msg);
-    }
+        if ((q = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return q;
+        if ((q = do_build(c)) != SG_OK) return q;
+        return do_density(c);
+    });
+    if (r != SG_OK) return r;
     if ((r = ens_gravity(e, pot)) != SG_OK) return r;
-    for (sg_ctx* c : e->c) {
-        if ((r = do_sph(c)) != SG_OK) return e->fail(r, c->msg);
+    return ens_each(e, [&](sg_ctx* c) {
+        sg_status q;
+        if ((q = do_sph(c)) != SG_OK) return q;
         do_combine(c);
         c->accel_after_predict = true;
-        if ((r = do_kick_drift(c, dt, SG_CORRECT)) != SG_OK) return e->fail(r, c->msg);
-    }
-    return SG_OK;
+        return do_kick_drift(c, dt, SG_CORRECT);
+    });
 }
 
 }  // namespace
+}  // extern "C++"
 
 size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles) {
     if (nsys < 1 || total_particles < 1) return 0;
@@ -937,6 +990,24 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // side streams for the systems' own launches (default priority)
+    const int nside = nsys < 8 ? nsys : 8;
+    for (int i = 0; i < nside; ++i) {
+        hipStream_t x = nullptr;
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) break;
+        e->side.push_back(x);
+    }
+    for (size_t i = 0; i < e->side.size() + 1; ++i) {
+        hipEvent_t x = nullptr;
+        if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) break;
+        e->ev.push_back(x);
+    }
+    if (e->ev.size() != e->side.size() + 1) {          // fall back to the shared stream
+        for (hipStream_t x : e->side) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : e->ev) (void)hipEventDestroy(x);
+        e->side.clear();
+        e->ev.clear();
+    }
     // persistent grid: as many workgroups as are resident at once
     const int per_cu = sg_grav_ensemble_blocks_per_cu(ipl, tile, 1);
     (void)hipGetLastError();
