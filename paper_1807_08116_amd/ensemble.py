@@ -7,8 +7,9 @@ FP32-compensated form.  Reports aggregate pair-interactions/s of the
 batched gravity and of per-system launches, and steps/s of graph-captured
 ensemble steps.
 
-With --tune the persistent launch's targets per lane and j-tile are first
-picked by the autotuner on these systems.
+With --tune the persistent launch's targets per lane (the block of
+targets) and j-tile are first picked by the autotuner on these systems,
+and the neighbour-grid cell size on the largest of them.
 
 Usage: python -m paper_1807_08116_amd.ensemble [--nsys 64] [--steps 50]
            [--reps 3] [--scale 1.0] [--tune]
@@ -49,6 +50,9 @@ def main():
         from paper_1807_08116_amd import autotune
         t = time.perf_counter()
         shape = autotune.tune_ensemble(states, reps=2, verbose=True)
+        # cell size of the neighbour grid, tuned on the largest system
+        big = max(states, key=lambda s: len(s["x"]))
+        shape["cell_scale_log2"] = autotune.tune_cells(big, sg.SG_FP32C, reps=2, verbose=True)
         log("autotuned ensemble launch %s (%.1fs)" % (shape, time.perf_counter() - t))
     ens = sg.Ensemble(states, **shape)
     st = ens.stream
