@@ -151,11 +151,14 @@ sg_status sg_bind_state(sg_ctx *ctx, int64_t n_gas, int64_t n_halo, const sg_sta
  * reproducible: d = (float)(r_i - r_j) per component (FP64 difference
  * rounded once), r2 = fmaf(dz,dz, fmaf(dy,dy, dx*dx)),
  * c = (float)h_i + (float)h_j, neighbour iff r2 < c*c.
- * Grid: levels l = 0,1,.. of cubic cells of side L_l = L_0 2^l, L_0 the
- * smallest power of two >= (2 + 2^-9) min h; particle i sits on the first
- * level with L_l >= (2 + 2^-9) h_i; each level covers the bounding box of
- * its own particles from origin floor(min/L_l) L_l; keys run level by
- * level, then z, y, x (x fastest). */
+ * Grid: levels l = 0,1,.. of cubic cells of side L_l = L_0 2^(l + s)
+ * (s = cell_scale_log2, 0 by default), L_0 the smallest power of two >=
+ * (2 + 2^-9) min h; particle i sits on the first level with L_0 2^l >=
+ * (2 + 2^-9) h_i; each level covers the bounding box of its own particles
+ * from origin floor(min/L_l) L_l; keys run level by level, then z, y, x
+ * (x fastest).  Device-side conditions (cells or neighbour pairs beyond
+ * the capacities, non-finite positions, h <= 0, more than SG_MAX_LEVELS
+ * levels) are latched and reported by the next sg_sync. */
 sg_status sg_build_neighbors(sg_ctx *ctx);
 
 /* SPH density of every gas particle (Eq. SPH-mass-density, self term
