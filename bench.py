@@ -94,6 +94,9 @@ def run_form(sg, st, precision, steps, warmup, sample, tune):
     ctx.compute_accel(sg.SG_SPH | sg.SG_GRAV | sg.SG_POT)
     ctx.sync()
     acc = np.stack([eng.dev[f][sample].cpu().numpy() for f in ("ax", "ay", "az")], 1)
+    ng = st["ng"]
+    parts = {"grav": ctx.export(sg.SG_X_ACC_GRAV)[:, sample].T,
+             "sph": ctx.export(sg.SG_X_ACC_SPH)[:, sample[sample < ng]].T}
     diag = ctx.diagnostics()
     for _ in range(warmup):
         ctx.step(DT, sg.SG_POT)
@@ -116,8 +119,8 @@ def run_form(sg, st, precision, steps, warmup, sample, tune):
     eng.ctx.close()
     del eng
     torch.cuda.empty_cache()
-    return {"sec": (t1 - t0), "acc": acc, "prof": prof, "diag": d.tolist(), "nnz": nnz,
-            "ncell": ncell}
+    return {"sec": (t1 - t0), "acc": acc, "parts": parts, "prof": prof, "diag": d.tolist(),
+            "nnz": nnz, "ncell": ncell}
 
 
 def cpu_baseline(st, sample, prm):
@@ -143,11 +146,11 @@ def cpu_baseline(st, sample, prm):
     gx, gy, gz, gp = oracle.gravity(st["x"], st["y"], st["z"], st["m"], prm["G"], prm["eps"],
                                     sample)
     t_grav = time.perf_counter() - t
-    ref = np.stack([gx, gy, gz], 1)
     gas = sample < ng
-    ref[gas, 0] += asx[sample[gas]]
-    ref[gas, 1] += asy[sample[gas]]
-    ref[gas, 2] += asz[sample[gas]]
+    ref_grav = np.stack([gx, gy, gz], 1)
+    ref_sph = np.stack([asx[sample[gas]], asy[sample[gas]], asz[sample[gas]]], 1)
+    ref = ref_grav.copy()
+    ref[gas] += ref_sph
     step_s = t_nbr + t_dens + 2 * t_sph + t_grav * n / len(sample)
     cores = oracle.get_threads()
     # one thread: density, forces and gravity of 256 of the targets (the
@@ -169,7 +172,7 @@ def cpu_baseline(st, sample, prm):
     finally:
         oracle.set_threads(cores)
     step1_s = t_nbr + t1_dens + 2 * t1_sph + t1_grav * n / len(s1)
-    return ref, {
+    return {"total": ref, "grav": ref_grav, "sph": ref_sph}, {
         "value": 1.0 / step_s, "unit": "force-steps/s", "cores": cores, "kind": "oracle",
         "sample": ("gravity of %d seeded targets over all %d sources (x%.0f to a step) + whole "
                    "SPH part (neighbours %.1fs, density %.1fs, forces %.1fs x2); gravity %.1fs"
@@ -234,7 +237,13 @@ def main():
         log("oracle baseline on the host ...")
         ref, cpu = cpu_baseline(st, sample, prm)
         for form in forms:
-            errs[form] = nrm_err(res[form]["acc"], ref)
+            r = res[form]
+            errs[form] = nrm_err(r["acc"], ref["total"])
+            rel = (np.linalg.norm(r["acc"] - ref["total"], axis=1)
+                   / np.linalg.norm(ref["total"], axis=1))
+            r["err_parts"] = {"gravity": nrm_err(r["parts"]["grav"], ref["grav"]),
+                              "sph": nrm_err(r["parts"]["sph"], ref["sph"]),
+                              "median_particle_rel": float(np.median(rel))}
         log("  oracle %.4g steps/s (extrapolated); errors %s" % (cpu["value"], errs))
 
     head = "fp32c" if "fp32c" in res else "fp64"
@@ -279,6 +288,7 @@ def main():
             "stage_ms_per_step": {k: v[0] / args.steps for k, v in pr.items()},
             "grav_ms_per_launch": pr["grav"][0] / max(pr["grav"][1], 1),
             "accel_err": errs.get(form),
+            "accel_err_parts": res[form].get("err_parts"),
             "diagnostics_last": res[form]["diag"],
             "nnz": res[form]["nnz"],
             "hbm_passes": hbm_passes(form, pr, ng, res[form]["nnz"], res[form]["ncell"]),

@@ -227,7 +227,13 @@ typedef enum {
     SG_X_NBR_OFF = 5,   /* int64 [N_g+1] CSR row offsets, rows by slot       */
     SG_X_NBR_IDX = 6,   /* int32 [nnz] neighbour slots, ascending per row    */
     SG_X_GRID = 7,      /* sg_grid_info, 1 element                           */
-    SG_X_GORDER = 8     /* int32 [N] gravity target order (SG_FP32C, FP64 grav_variant 3/4) */
+    SG_X_GORDER = 8,    /* int32 [N] gravity target order (SG_FP32C, FP64 grav_variant 3/4) */
+    SG_X_ACC_SPH = 9,   /* double [3 N_g] latest SPH part of the acceleration (Eq.
+                           dv_dt-SPH): all x, then all y, then all z, by gas
+                           particle index; SG_ESTATE before any SG_SPH      */
+    SG_X_ACC_GRAV = 10  /* double [3 N] latest gravity part (Eq. self-gravity, G
+                           applied), same layout over all particles;
+                           SG_ESTATE before any SG_GRAV                     */
 } sg_export_what;
 
 /* Host-readable grid description (SG_X_GRID): L0 is the base of the level

@@ -736,6 +736,24 @@ sg_status sg_export(sg_ctx* c, int32_t what, void* dst, int64_t cap_bytes, int64
         case SG_X_GORDER:
             if (!uses_morton(c->prm)) return c->fail(SG_EINVAL, "no gravity order for this kernel");
             src = c->at<void>(c->L.gorder); n = c->n; esz = 4; break;
+        case SG_X_ACC_SPH:
+        case SG_X_ACC_GRAV: {
+            // three component arrays, copied one after the other
+            const bool sph = what == SG_X_ACC_SPH;
+            if (sph ? !c->have_sph : !c->have_grav)
+                return c->fail(SG_ESTATE, sph ? "no SPH acceleration computed yet"
+                                              : "no gravity computed yet");
+            const int64_t len = sph ? ng : c->n;
+            *n_out = 3 * len;
+            if (3 * len * 8 > cap_bytes) return c->fail(SG_ECAPACITY, "destination too small");
+            const size_t part[3] = {sph ? c->L.asx : c->L.gx, sph ? c->L.asy : c->L.gy,
+                                    sph ? c->L.asz : c->L.gz};
+            for (int d = 0; d < 3 && len > 0; ++d)
+                if (hipMemcpy(static_cast<char*>(dst) + (size_t)d * len * 8, c->at<void>(part[d]),
+                              (size_t)len * 8, hipMemcpyDeviceToDevice) != hipSuccess)
+                    return c->fail(SG_EDEVICE, "export copy failed");
+            return SG_OK;
+        }
         case SG_X_GRID: {
             if (cap_bytes < (int64_t)sizeof(sg_grid_info)) return c->fail(SG_ECAPACITY, "buffer too small");
             sg_grid_info info;

@@ -24,7 +24,7 @@ SG_SPH, SG_GRAV, SG_POT = 1, 2, 4
 SG_PREDICT, SG_CORRECT = 0, 1
 SG_MAX_LEVELS = 16
 (SG_X_KEYS, SG_X_COUNTS, SG_X_OFFSETS, SG_X_HMAX, SG_X_PERM, SG_X_NBR_OFF, SG_X_NBR_IDX,
- SG_X_GRID, SG_X_GORDER) = range(9)
+ SG_X_GRID, SG_X_GORDER, SG_X_ACC_SPH, SG_X_ACC_GRAV) = range(11)
 
 STATUS_NAMES = {0: "SG_OK", 1: "SG_EINVAL", 2: "SG_ECAPACITY", 3: "SG_EDEVICE", 4: "SG_ESTATE",
                 5: "SG_ENONFINITE", 6: "SG_ERANGE"}
@@ -292,7 +292,8 @@ class Context:
 
     _EXPORT_DTYPES = {SG_X_KEYS: "int32", SG_X_COUNTS: "int32", SG_X_OFFSETS: "int64",
                       SG_X_HMAX: "uint64", SG_X_PERM: "int32", SG_X_NBR_OFF: "int64",
-                      SG_X_NBR_IDX: "int32", SG_X_GORDER: "int32"}
+                      SG_X_NBR_IDX: "int32", SG_X_GORDER: "int32", SG_X_ACC_SPH: "float64",
+                      SG_X_ACC_GRAV: "float64"}
 
     def export(self, what):
         """Copy an internal array out (syncs the stream); returns a numpy array."""
@@ -319,6 +320,8 @@ class Context:
             arr = raw.view(np.dtype(dt))
             if what == SG_X_HMAX:
                 arr = arr.view(np.float64)
+            if what in (SG_X_ACC_SPH, SG_X_ACC_GRAV):
+                arr = arr.reshape(3, -1)         # rows x, y, z
             return arr.copy()
         raise SGError(SG_ECAPACITY, "export size changed")
 

@@ -25,6 +25,23 @@ def test_header_symbols_exported(sg):
         assert hasattr(L, name), name
 
 
+def test_binding_constants_match_header(sg):
+    # every enumerator and flag the header defines has the same value in the
+    # binding (status codes, precision forms, flags, exports, stages)
+    hdr = open(os.path.join(ROOT, "include", "sphgrav.h")).read()
+    enum = dict(re.findall(r"^\s+(SG_[A-Z0-9_]+)\s*=\s*(\d+)", hdr, re.M))
+    defs = dict(re.findall(r"^#define\s+(SG_[A-Z0-9_]+)\s+(\d+)u?\b", hdr, re.M))
+    assert "SG_X_ACC_GRAV" in enum and "SG_POT" in defs
+    for name, v in list(enum.items()) + list(defs.items()):
+        if name == "SG_NSTAGE":
+            assert len(sg.STAGES) == int(v)
+        elif name.startswith("SG_ST_"):          # stages: the binding's STAGES list
+            assert sg.STAGES[int(v)] == name[len("SG_ST_"):].lower(), name
+        else:
+            assert hasattr(sg, name), name
+            assert getattr(sg, name) == int(v), name
+
+
 def test_struct_sizes_match_header(sg):
     # sg_params: 6 doubles + 8 int32; sg_caps: 4 int64; sg_state: 15 pointers
     assert C.sizeof(sg.Params) == 6 * 8 + 8 * 4

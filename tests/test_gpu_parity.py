@@ -141,6 +141,31 @@ def test_c0_forces(sg, orc, c0, c0_ref, precision):
     assert e_pot < tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_c0_force_parts(sg, orc, c0, c0_ref, precision):
+    # the SPH and gravity parts separately (the FP32C form's error is
+    # reported per part), and their sum is what the state holds
+    ref, s, soff, sidx = c0_ref
+    p = sg.SG_FP64 if precision == "fp64" else sg.SG_FP32C
+    tol = FP64_TOL if precision == "fp64" else FP32C_TOL
+    eng = sg.Engine(c0, precision=p)
+    with pytest.raises(sg.SGError) as ei:
+        eng.ctx.export(sg.SG_X_ACC_GRAV)
+    assert ei.value.code == sg.SG_ESTATE
+    full_eval(eng, sg)
+    ng, n = c0["ng"], len(c0["x"])
+    a_sph = eng.ctx.export(sg.SG_X_ACC_SPH)
+    a_grav = eng.ctx.export(sg.SG_X_ACC_GRAV)
+    assert a_sph.shape == (3, ng) and a_grav.shape == (3, n)
+    e_sph = nrm_err(a_sph.T, np.stack([ref["asx"], ref["asy"], ref["asz"]], 1))
+    e_grav = nrm_err(a_grav.T, np.stack([ref["gx"], ref["gy"], ref["gz"]], 1))
+    print(precision, "sph part", e_sph, "gravity part", e_grav)
+    assert e_sph < tol and e_grav < tol
+    tot = a_grav.copy()
+    tot[:, :ng] += a_sph
+    np.testing.assert_array_equal(tot.T, gpu_accel(eng))
+
+
 # (targets per lane, source splits, FP64 variant, j-tile); the FP32C form
 # has one kernel and takes the same shapes with variant 0
 @pytest.mark.parametrize("ipl,split,variant,tile", [
