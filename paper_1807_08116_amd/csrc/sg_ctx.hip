@@ -322,7 +322,7 @@ sg_status do_build(sg_ctx* c) {
     int32_t* ncnt = c->at<int32_t>(c->L.ncnt);
     int64_t* nbr_off = c->at<int64_t>(c->L.nbr_off);
     int32_t* slots = c->at<int32_t>(c->L.nbr_slots);
-    sg_launch_nbr_search(g, ng, b.xs, b.ys, b.zs, b.hs, off, ncnt, slots, st);
+    sg_launch_nbr_search(g, ng, b.xs, b.ys, b.zs, b.hs, off, b.perm, key, ncnt, slots, st);
     sg_launch_scan(ncnt, nbr_off, ng, nullptr, ng, scan, st);
     sg_launch_nbr_check(g, nbr_off, ng, c->caps.nnz_cap, st);
     sg_launch_nbr_compact(g, ng, b.xs, b.ys, b.zs, b.hs, off, ncnt, slots, nbr_off,

@@ -100,8 +100,9 @@ void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
 // counts, then (after the scan and the capacity check) the copy into CSR.
 size_t sg_nbr_slot_bytes(int64_t ng);
 void sg_launch_nbr_search(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
-                          const double* zs, const double* hs, const int64_t* off, int32_t* cnt,
-                          int32_t* slots, hipStream_t st);
+                          const double* zs, const double* hs, const int64_t* off,
+                          const int32_t* perm, const int32_t* key, int32_t* cnt, int32_t* slots,
+                          hipStream_t st);
 void sg_launch_nbr_check(sg_grid_dev* g, const int64_t* nbr_off, int64_t ng, int64_t nnz_cap,
                          hipStream_t st);
 void sg_launch_nbr_compact(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,

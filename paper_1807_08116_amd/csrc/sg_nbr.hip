@@ -2,22 +2,30 @@
 // kernels build from CellSPH / indexPC / hmaxCell, Sec. 3), stored as CSR
 // by sorted slot.
 //
-// One wavefront per target slot s.  For every non-empty level l the target
-// scans the cells within R = (h_s + hmax_l)(1 + 2^-10) of itself: any pair
-// passing the predicate has |r| < (h_s + h_t)(1 + 2^-20) <= R, so the scan
-// is complete.  Cells with the same (level, z, y) and consecutive x are
-// consecutive in key order, so each (z, y) row of the box is one contiguous
-// slot range, read with coalesced loads, 64 candidates at a time; the
-// bounds of up to 64 rows are fetched at once, one row per lane.  Levels
-// ascend, then z, y, x, so slots come out in ascending order and rows need
-// no sort.
+// Search region.  For every non-empty level l a target s must scan the
+// cells within R = (h_s + hmax_l)(1 + 2^-10) of itself: any pair passing
+// the predicate has |r| < (h_s + h_t)(1 + 2^-20) <= R, so the scan is
+// complete.  Cells with the same (level, z, y) and consecutive x are
+// consecutive in key order, so each (z, y) row of a box of cells is one
+// contiguous slot range, and visiting levels, then z, y, x in ascending
+// order yields candidates in ascending slot order: rows need no sort.
 //
-// One search pass: each target writes its hits into a slot of its own,
-// kSlot entries long, in a scratch array (no atomics), and counts them.  A
-// scan of the counts gives the CSR offsets; a copy pass then moves every
-// slot to its CSR row, and a target with more than kSlot hits (none in the
-// workloads measured: at most 58) searches a second time, straight into
-// its row.
+// Cell-staged search (k_nbr_search).  One wavefront takes 64 consecutive
+// target slots and walks them cell by cell: the targets that share a cell
+// key form a run, and the run's search region is the union (per level) of
+// its targets' boxes.  The rows of that region are flattened into one
+// candidate stream, loaded 64 candidates at a time (one per lane) and held
+// in registers while every target of the run tests them, so a candidate
+// is fetched once per cell instead of once per target.  Any grouping gives
+// the same lists: the union contains each target's own box, and every
+// target keeps only the candidates that pass its predicate, in stream
+// order.
+//
+// Each target writes its hits into a slot of its own, kSlot entries long,
+// in a scratch array (no atomics), and counts them.  A scan of the counts
+// gives the CSR offsets; a copy pass then moves every slot to its CSR row,
+// and a target with more than kSlot hits (none in the workloads measured:
+// at most 58) searches a second time, alone, straight into its row.
 //
 // Built with -ffp-contract=off: the FP32 predicate must round exactly as
 // specified (each product and fma rounded once).
@@ -46,8 +54,43 @@ __device__ inline bool nbr_pred(double xi, double yi, double zi, float hif, doub
     return r2 < cut2;
 }
 
+// The same predicate with the candidate's h already rounded to FP32.
+__device__ inline bool nbr_pred_f(double xi, double yi, double zi, float hif, double xj,
+                                  double yj, double zj, float hjf) {
+    const float dx = (float)(xi - xj);
+    const float dy = (float)(yi - yj);
+    const float dz = (float)(zi - zj);
+    const float dxx = dx * dx;
+    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+    const float cut = hif + hjf;
+    const float cut2 = cut * cut;
+    return r2 < cut2;
+}
+
 constexpr int64_t kSlot = 96;              // scratch entries per target
 
+// Cells [lo, hi] (per dimension, clamped to the grid) of level l within
+// R = (h + hmax_l)(1 + 2^-10) of p; false when the level has no such cell.
+__device__ inline bool level_box(const sg_grid_dev* __restrict__ g, int l, const double p[3],
+                                 double h, int64_t lo[3], int64_t hi3[3]) {
+    const double R = (h + g->hmaxlev[l]) * (1.0 + 0x1p-10);
+    const double inv = g->invL[l];
+    bool empty = false;
+    for (int d = 0; d < 3; ++d) {
+        const double o = g->org[l][d];
+        const double top = (double)(g->dim[l][d] - 1);
+        double a = floor((p[d] - R - o) * inv);
+        double b = floor((p[d] + R - o) * inv);
+        if (b < 0.0 || a > top) empty = true;
+        a = a < 0.0 ? 0.0 : (a > top ? top : a);
+        b = b < 0.0 ? 0.0 : (b > top ? top : b);
+        lo[d] = (int64_t)a;
+        hi3[d] = (int64_t)b;
+    }
+    return !empty;
+}
+
+// One target's scan over its own boxes (used by the overflow path).
 template <typename F>
 __device__ inline void nbr_scan(const sg_grid_dev* __restrict__ g, int64_t ng, int64_t s,
                                 unsigned lane, const double* __restrict__ xs,
@@ -59,24 +102,9 @@ __device__ inline void nbr_scan(const sg_grid_dev* __restrict__ g, int64_t ng, i
     const float hif = (float)hi;
     const int nlev = g->nlev;
     for (int l = 0; l < nlev; ++l) {
-        const int64_t ncell = g->ncell[l];
-        if (ncell == 0) continue;
-        const double R = (hi + g->hmaxlev[l]) * (1.0 + 0x1p-10);
-        const double inv = g->invL[l];
+        if (g->ncell[l] == 0) continue;
         int64_t lo[3], hi3[3];
-        bool empty = false;
-        for (int d = 0; d < 3; ++d) {
-            const double o = g->org[l][d];
-            const double top = (double)(g->dim[l][d] - 1);
-            double a = floor((p[d] - R - o) * inv);
-            double b = floor((p[d] + R - o) * inv);
-            if (b < 0.0 || a > top) empty = true;
-            a = a < 0.0 ? 0.0 : (a > top ? top : a);
-            b = b < 0.0 ? 0.0 : (b > top ? top : b);
-            lo[d] = (int64_t)a;
-            hi3[d] = (int64_t)b;
-        }
-        if (empty) continue;
+        if (!level_box(g, l, p, hi, lo, hi3)) continue;
         const int64_t base = g->base[l], dx = g->dim[l][0], dy = g->dim[l][1];
         const int64_t ny = hi3[1] - lo[1] + 1;
         const int64_t nrows = (hi3[2] - lo[2] + 1) * ny;
@@ -108,24 +136,161 @@ __device__ inline void nbr_scan(const sg_grid_dev* __restrict__ g, int64_t ng, i
     }
 }
 
+__device__ inline int32_t wave_min(int32_t v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int32_t u = __shfl_xor(v, o, 64);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+__device__ inline int32_t wave_max(int32_t v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int32_t u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// inclusive prefix sum over the 64 lanes
+__device__ inline int32_t wave_incl_sum(int32_t v, unsigned lane) {
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(v, o, 64);
+        if (lane >= (unsigned)o) v += u;
+    }
+    return v;
+}
+
+__device__ inline double lane_f64(double v, int L) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, L);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), L);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ inline float lane_f32(float v, int L) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), L));
+}
+
 __global__ __launch_bounds__(kBlock) void k_nbr_search(
     const sg_grid_dev* __restrict__ g, int64_t ng, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ hs,
-    const int64_t* __restrict__ off, int32_t* __restrict__ cnt, int32_t* __restrict__ slots) {
+    const int64_t* __restrict__ off, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ key, int32_t* __restrict__ cnt, int32_t* __restrict__ slots) {
     if (g->err & SGE_SORT_FATAL) return;
     const unsigned lane = threadIdx.x & 63;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-    if (s >= ng) return;                       // uniform per wave
-    int32_t* mine = slots + s * kSlot;
-    int64_t c = 0;
-    nbr_scan(g, ng, s, lane, xs, ys, zs, hs, off, [&](unsigned long long mask, int64_t t, bool ok) {
-        if (ok) {
-            const int64_t pos = c + rank_below(mask);
-            if (pos < kSlot) mine[pos] = (int32_t)t;
+    // first target slot of this wavefront (uniform: held in a scalar register)
+    const int32_t w = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
+    const int64_t g0 = (int64_t)w * 64;
+    if (g0 >= ng) return;
+    const int64_t s = g0 + lane;
+    const bool live = s < ng;
+    double p[3] = {0.0, 0.0, 0.0}, h = 0.0;
+    int32_t k = -1;
+    if (live) {
+        p[0] = xs[s];
+        p[1] = ys[s];
+        p[2] = zs[s];
+        h = hs[s];
+        const int32_t i = perm[s];
+        // the key only groups targets (any grouping is correct)
+        k = (uint32_t)i < (uint64_t)ng ? key[i] : -2 - (int32_t)lane;
+    }
+    const float hif = (float)h;
+    int32_t mine = 0;                          // hits of target g0 + lane so far
+    const int nlev = g->nlev;
+    unsigned long long todo = __ballot(live);
+    while (todo) {
+        const int lead = __builtin_ctzll(todo);
+        const int32_t rk = __builtin_amdgcn_readlane(k, lead);
+        const unsigned long long run = __ballot(live && k == rk) & todo;
+        todo &= ~run;
+        const bool inrun = (run >> lane) & 1ull;
+        for (int l = 0; l < nlev; ++l) {
+            if (g->ncell[l] == 0) continue;
+            int64_t lo[3], hi3[3];
+            const bool has = inrun && level_box(g, l, p, h, lo, hi3);
+            // union of the run's boxes (cell indices fit int32: keys do);
+            // wave-uniform, held in scalar registers so that every loop
+            // below is uniform and its cross-lane reads see all lanes
+            int32_t ulo[3], uhi[3];
+            for (int d = 0; d < 3; ++d) {
+                ulo[d] = __builtin_amdgcn_readfirstlane(wave_min(has ? (int32_t)lo[d] : INT32_MAX));
+                uhi[d] = __builtin_amdgcn_readfirstlane(wave_max(has ? (int32_t)hi3[d] : -1));
+            }
+            if (uhi[0] < 0) continue;          // no target of the run reaches level l
+            const int64_t base = g->base[l], dx = g->dim[l][0], dy = g->dim[l][1];
+            const int64_t ny = (int64_t)uhi[1] - ulo[1] + 1;
+            const int64_t nrows = ((int64_t)uhi[2] - ulo[2] + 1) * ny;
+            for (int64_t r0 = 0; r0 < nrows; r0 += 64) {
+                // rows r0 .. r0+63, one per lane: first slot and length
+                // (offsets clamped to [0, ng] so that a corrupt table can
+                // never send a load outside the sorted arrays)
+                int32_t first = 0, len = 0;
+                const int64_t r = r0 + lane;
+                if (r < nrows) {
+                    const int64_t cz = ulo[2] + r / ny, cy = ulo[1] + r % ny;
+                    const int64_t row = base + (cz * dy + cy) * dx;
+                    int64_t a = off[row + ulo[0]], b = off[row + uhi[0] + 1];
+                    a = a < 0 ? 0 : (a > ng ? ng : a);
+                    b = b < a ? a : (b > ng ? ng : b);
+                    first = (int32_t)a;
+                    len = (int32_t)(b - a);
+                }
+                // flatten: the rows are disjoint slot ranges, so the total
+                // is at most ng
+                const int32_t incl = wave_incl_sum(len, lane);
+                const int32_t start = incl - len;
+                const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+                // stream position q -> slot: the row holding q is the last
+                // row whose start is <= q (starts do not decrease)
+                auto locate = [&](int32_t q) -> int64_t {
+                    int rr = 0;
+                    for (int step = 32; step >= 1; step >>= 1) {
+                        const int mid = rr + step;
+                        if (__shfl(start, mid, 64) <= q) rr = mid;
+                    }
+                    return (int64_t)__shfl(first, rr, 64) + (q - __shfl(start, rr, 64));
+                };
+                for (int32_t cb = 0; cb < total; cb += 64) {
+                    const int32_t q = cb + (int32_t)lane;
+                    const bool valid = q < total;
+                    const int64_t t = locate(q);
+                    const int32_t trel = (int32_t)(t - g0);      // |t - g0| < ng
+                    double xj = 0.0, yj = 0.0, zj = 0.0;
+                    float hjf = 0.f;
+                    if (valid) {
+                        xj = xs[t];
+                        yj = ys[t];
+                        zj = zs[t];
+                        hjf = (float)hs[t];
+                    }
+                    // every target of the run against these 64 candidates
+                    for (unsigned long long tr = run; tr; tr &= tr - 1) {
+                        const int L = __builtin_ctzll(tr);
+                        const int64_t sL = g0 + L;
+                        // target L's data, read across lanes with every lane
+                        // active (a lane read inside a divergent branch may
+                        // see a register the branch did not write for it)
+                        const double xi = lane_f64(p[0], L), yi = lane_f64(p[1], L);
+                        const double zi = lane_f64(p[2], L);
+                        const float hi = lane_f32(hif, L);
+                        const bool ok = nbr_pred_f(xi, yi, zi, hi, xj, yj, zj, hjf) & valid &
+                                        (trel != L);
+                        const unsigned long long mask = __ballot(ok);
+                        if (mask) {
+                            const int32_t c0 = __builtin_amdgcn_readlane(mine, L);
+                            const int32_t pos = c0 + (int32_t)rank_below(mask);
+                            if (ok && pos < kSlot) slots[sL * kSlot + pos] = (int32_t)t;
+                            if (lane == (unsigned)L) mine = c0 + __builtin_popcountll(mask);
+                        }
+                    }
+                }
+            }
         }
-        c += __builtin_popcountll(mask);
-    });
-    if (lane == 0) cnt[s] = (int32_t)c;
+    }
+    if (live) cnt[s] = mine;
 }
 
 // Move every target's slot to its CSR row (or search again into the row
@@ -175,10 +340,12 @@ inline unsigned waves_grid(int64_t n) {
 size_t sg_nbr_slot_bytes(int64_t ng) { return 4 * (size_t)kSlot * (size_t)(ng > 0 ? ng : 0); }
 
 void sg_launch_nbr_search(const sg_grid_dev* g, int64_t ng, const double* xs, const double* ys,
-                          const double* zs, const double* hs, const int64_t* off, int32_t* cnt,
-                          int32_t* slots, hipStream_t st) {
-    hipLaunchKernelGGL(k_nbr_search, dim3(waves_grid(ng)), dim3(kBlock), 0, st, g, ng, xs, ys, zs,
-                       hs, off, cnt, slots);
+                          const double* zs, const double* hs, const int64_t* off,
+                          const int32_t* perm, const int32_t* key, int32_t* cnt, int32_t* slots,
+                          hipStream_t st) {
+    // one wavefront per 64 target slots
+    hipLaunchKernelGGL(k_nbr_search, dim3(waves_grid((ng + 63) / 64)), dim3(kBlock), 0, st, g, ng,
+                       xs, ys, zs, hs, off, perm, key, cnt, slots);
 }
 
 void sg_launch_nbr_check(sg_grid_dev* g, const int64_t* nbr_off, int64_t ng, int64_t nnz_cap,
