@@ -1,7 +1,10 @@
 """Ensembles: gravity of several systems in one persistent launch equals
 each system's own gravity (same kernel body, same targets per workgroup);
 ensemble steps equal per-system steps; graph replays equal eager ensemble
-steps."""
+steps.  At the full ensemble size (64 systems, 4659360 particles), in the
+tuned launch: batched gravity equals the systems' own launches bit for bit
+on four systems (largest, smallest, two others) and the oracle on 256
+seeded targets of each; one ensemble step keeps every system's momentum."""
 import numpy as np
 import pytest
 
@@ -62,3 +65,47 @@ def test_ensemble_steps_match_single_and_graph(sg, states):
             a, b, c = e1.numpy(f), e2.numpy(f), single.numpy(f)
             np.testing.assert_array_equal(a, b, err_msg="graph " + f)
             np.testing.assert_array_equal(a, c, err_msg="single " + f)
+
+
+# ------------------------------------------------- full ensemble size --
+
+@pytest.fixture(scope="module")
+def c4():
+    from paper_1807_08116_amd import ic
+    return ic.ensemble()          # 64 systems, N log-uniform in [8192, 262144]: 4659360 particles
+
+
+def test_c4_fullsize(sg, orc, c4):
+    # the launch the ensemble benchmark tunes to (IPL 2, j-tile 512)
+    ens = sg.Ensemble(c4, grav_ipl=2, grav_tile=512)
+    ens.gravity(sg.SG_GRAV | sg.SG_POT)
+    ens.torch.cuda.synchronize()
+    ns = [len(s["x"]) for s in c4]
+    print("c4: %d systems, %d particles" % (len(c4), sum(ns)), flush=True)
+    rng = np.random.default_rng(7)
+    for k in sorted({int(np.argmax(ns)), int(np.argmin(ns)), 17, 40}):
+        st, eng = c4[k], ens.engines[k]
+        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_ipl=2, grav_tile=512)
+        single.ctx.compute_accel(sg.SG_GRAV | sg.SG_POT)
+        single.ctx.sync()
+        for f in ("ax", "ay", "az", "pot"):
+            np.testing.assert_array_equal(eng.numpy(f), single.numpy(f), err_msg="%d %s" % (k, f))
+        single.ctx.close()
+        t = np.sort(rng.choice(ns[k], 256, replace=False))
+        gx, gy, gz, gp = orc.gravity(st["x"], st["y"], st["z"], st["m"], 1.0, 0.01, t)
+        ref = np.stack([gx, gy, gz], 1)
+        got = np.stack([eng.numpy(f)[t] for f in ("ax", "ay", "az")], 1)
+        e_acc = np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2))
+        e_pot = np.sqrt(np.sum((eng.numpy("pot")[t] - gp) ** 2) / np.sum(gp ** 2))
+        print("system %d N %d gravity err %.2e pot err %.2e" % (k, ns[k], e_acc, e_pot))
+        assert e_acc < 1e-6 and e_pot < 1e-6
+    # one whole ensemble step: every system's momentum is kept to the
+    # rounding of its FP32 pair sums (forces are pairwise antisymmetric)
+    p0 = [np.array([np.sum(s["m"] * s[f]) for f in ("vx", "vy", "vz")]) for s in c4]
+    ens.run(1e-3, 1, sg.SG_POT, use_graph=False)
+    for s, eng, q0 in zip(c4, ens.engines, p0):
+        m = s["m"]
+        scale = np.sum(m * np.sqrt(s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2))
+        q1 = np.array([np.sum(m * eng.numpy(f)) for f in ("vx", "vy", "vz")])
+        assert np.all(np.isfinite(q1))
+        assert np.all(np.abs(q1 - q0) < 1e-7 * scale)
