@@ -174,13 +174,17 @@ __device__ inline double box_gap2(const box6& a, const box6& b) {
 // rounding error of both rewritings to a few units of 2^-24 per pair.  The
 // two sums are kept apart (Kahan-compensated FP32 over tiles) and combined
 // in FP64 at the end; near-field contributions are added to the first sum
-// directly.  The near/far choice is uniform across the workgroup.
+// directly.  Each wavefront owns 64*IPL consecutive targets; the near/far
+// choice of a sub-tile is uniform across the wavefront and tests the gap
+// between the sub-tile's box and the box of the wavefront's own targets
+// against D/8 of the workgroup box (the anchor's scale), so the bound above
+// holds unchanged while fewer sub-tiles take the near-field path.
 template <int TILE>
 struct f32c_lds {
     float4 b[2][TILE];         // (-2 hi_x, -2 hi_y, -2 hi_z, |x|^2)
     float4 w[2][TILE];         // (m hi_x, m hi_y, m hi_z, m)
     float4 lo[2][TILE];        // (lo_x, lo_y, lo_z, 0)
-    int near[2][TILE / kSub];
+    int near[2][kBlock / 64][TILE / kSub];   // per wavefront
 };
 
 // One workgroup task: targets ib .. ib + 256*IPL - 1 (sorted order) against
@@ -218,13 +222,32 @@ __device__ __attribute__((always_inline)) inline void f32c_task(
     double diag2 = 0.0;
     for (int d = 0; d < 3; ++d) diag2 += (bb.hi[d] - bb.lo[d]) * (bb.hi[d] - bb.lo[d]);
     const double near2 = kNearFrac * kNearFrac * diag2;
+    // this wavefront's targets: ib + wv*64*IPL .. + 64*IPL - 1, lane + 64 k;
+    // their box from the IPL sub-tile boxes (the workgroup box if none is
+    // in range)
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int64_t iw = ib + (int64_t)wv * 64 * IPL;
+    box6 wb = bb;
+    {
+        const int64_t q0 = iw / kSub, nsub = (n + kSub - 1) / kSub;
+        if (q0 < nsub) {
+            wb = sbox[q0];
+            for (int64_t q = q0 + 1; q < q0 + IPL && q < nsub; ++q) {
+                const box6 o = sbox[q];
+                for (int d = 0; d < 3; ++d) {
+                    wb.lo[d] = o.lo[d] < wb.lo[d] ? o.lo[d] : wb.lo[d];
+                    wb.hi[d] = o.hi[d] > wb.hi[d] ? o.hi[d] : wb.hi[d];
+                }
+            }
+        }
+    }
 
     float xh[IPL], yh[IPL], zh[IPL], xl[IPL], yl[IPL], zl[IPL], ck[IPL];
     float fx[IPL], fy[IPL], fz[IPL], f1[IPL], fp[IPL];
     kahan sx[IPL], sy[IPL], sz[IPL], s1[IPL], sp[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        int64_t i = ib + k * kBlock + tid;
+        int64_t i = iw + k * 64 + lane;
         if (i >= n) i = ib;
         const double dx = xs[i] - Px, dy = ys[i] - Py, dz = zs[i] - Pz;
         xh[k] = (float)dx;
@@ -258,11 +281,11 @@ __device__ __attribute__((always_inline)) inline void f32c_task(
             L.w[buf][jl] = w;
             L.lo[buf][jl] = l;
         }
-        if (tid < TILE / kSub) {
-            const int64_t q = jt / kSub + tid;
+        if (lane < TILE / kSub) {
+            const int64_t q = jt / kSub + lane;
             int nr = 0;
-            if (jt + (int64_t)tid * kSub < j1) nr = box_gap2(bb, sbox[q]) < near2;
-            L.near[buf][tid] = nr;
+            if (jt + (int64_t)lane * kSub < j1) nr = box_gap2(wb, sbox[q]) < near2;
+            L.near[buf][wv][lane] = nr;
         }
     };
 
@@ -274,7 +297,7 @@ __device__ __attribute__((always_inline)) inline void f32c_task(
 #pragma unroll
         for (int k = 0; k < IPL; ++k) fx[k] = fy[k] = fz[k] = f1[k] = fp[k] = 0.0f;
         for (int sb = 0; sb < TILE / kSub; ++sb) {
-            if (L.near[cur][sb]) {
+            if (L.near[cur][wv][sb]) {
 #pragma unroll 2
                 for (int jj = sb * kSub; jj < (sb + 1) * kSub; ++jj) {
                     const float4 b = L.b[cur][jj];
@@ -332,7 +355,7 @@ __device__ __attribute__((always_inline)) inline void f32c_task(
     }
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        const int64_t i = ib + k * kBlock + tid;
+        const int64_t i = iw + k * 64 + lane;
         if (i >= n) continue;
         int32_t t = order[i];
         if ((uint64_t)t >= (uint64_t)n) continue;
