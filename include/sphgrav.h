@@ -16,7 +16,11 @@
  *   only the small opaque context.
  * - Streams: all work is enqueued on the HIP stream given to sg_create();
  *   entry points return as soon as the work is enqueued.  Only
- *   sg_sync() and sg_export() wait for the stream.
+ *   sg_sync() and sg_export() wait for the stream.  Inside a step the
+ *   gravity runs on a second stream of the context's own (default
+ *   priority), forked from the given stream and joined back into it before
+ *   the step's last kernels, so every step stays ordered on the given
+ *   stream (and can be captured from it).
  * - Errors: every call returns an sg_status; nothing aborts and no C++
  *   exception crosses the ABI.  Argument errors are detected on the host
  *   before any HIP call.  Conditions only the device can see (capacity
@@ -182,7 +186,10 @@ sg_status sg_kick_drift(sg_ctx *ctx, double dt, int32_t phase);
 /* One whole step, enqueue-only: [first call: neighbours, density,
  * gravity] -> SPH(predictor) -> SG_PREDICT -> neighbours -> density ->
  * gravity (once per step, reused by the next predictor) -> SPH(corrector)
- * -> SG_CORRECT.  flags may add SG_POT. */
+ * -> SG_CORRECT.  After SG_PREDICT the gravity runs on the context's
+ * second stream beside the neighbours -> density -> SPH(corrector) chain
+ * (the two are independent); results equal the sequential order bit for
+ * bit.  flags may add SG_POT. */
 sg_status sg_step(sg_ctx *ctx, double dt, uint32_t flags);
 
 /* nsteps whole steps (as sg_step) with the conserved quantities of each
@@ -279,7 +286,11 @@ sg_status sg_ensemble_create(sg_ctx *const *ctxs, int32_t nsys, void *d_ws, size
 /* Batched gravity (flags SG_GRAV [| SG_POT]) for every system, then each
  * context's acceleration output is refreshed as in sg_compute_accel. */
 sg_status sg_ensemble_gravity(sg_ens *e, uint32_t flags);
-/* One predictor-corrector step of every system (as sg_step), gravity batched. */
+/* One predictor-corrector step of every system (as sg_step), gravity batched.
+ * The systems' own launches run on up to 8 side streams of the ensemble
+ * (default priority) forked from and joined back into the shared stream;
+ * after SG_PREDICT the batched gravity runs on the shared stream beside
+ * the systems' neighbours -> density -> SPH(corrector) chains. */
 sg_status sg_ensemble_step(sg_ens *e, double dt, uint32_t flags);
 /* nsteps ensemble steps; with use_graph the steady-state step is captured
  * once and replayed (as sg_run).  Waits for the stream. */

@@ -161,6 +161,10 @@ struct sg_ctx {
     layout L;
     char* ws;
     hipStream_t st;
+    // second stream of a step (gravity beside the neighbour/SPH chain) and
+    // its fork / join events; null when they could not be created
+    hipStream_t st2;
+    hipEvent_t ev_fork, ev_join;
     // bound state
     bool bound;
     int64_t ng, nh, n;
@@ -499,9 +503,36 @@ sg_status do_step(sg_ctx* c, double dt, uint32_t flags) {
     if ((r = do_sph(c)) != SG_OK) return r;                 // predictor right-hand side
     do_combine(c);
     if ((r = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return r;
-    if ((r = do_build(c)) != SG_OK) return r;
-    if ((r = do_density(c)) != SG_OK) return r;
-    if ((r = do_accel(c, gflags | SG_SPH)) != SG_OK) return r;   // corrector right-hand side
+    // corrector right-hand side.  Gravity at the predicted positions and the
+    // neighbour build -> density -> SPH forces chain are independent: with a
+    // second stream, gravity runs there (forked from and joined back into
+    // the context's stream, also while it is being captured) and the chain
+    // on the context's stream.  They touch disjoint workspace buffers and
+    // disjoint fields of the grid record (the status word by atomic OR).
+    if (!c->st2) {
+        if ((r = do_build(c)) != SG_OK) return r;
+        if ((r = do_density(c)) != SG_OK) return r;
+        if ((r = do_accel(c, gflags | SG_SPH)) != SG_OK) return r;
+        return do_kick_drift(c, dt, SG_CORRECT);
+    }
+    if (hipEventRecord(c->ev_fork, c->st) != hipSuccess ||
+        hipStreamWaitEvent(c->st2, c->ev_fork, 0) != hipSuccess)
+        return c->fail(SG_EDEVICE, "step: fork to the gravity stream failed");
+    hipStream_t own = c->st;
+    c->st = c->st2;
+    sg_status rg = do_gravity(c, (flags & SG_POT) != 0);
+    c->st = own;
+    sg_status rs = rg != SG_OK ? rg : do_build(c);
+    if (rs == SG_OK) rs = do_density(c);
+    if (rs == SG_OK) rs = do_sph(c);
+    // join (also after an error, so that a capture stays whole)
+    if ((hipEventRecord(c->ev_join, c->st2) != hipSuccess ||
+         hipStreamWaitEvent(c->st, c->ev_join, 0) != hipSuccess) && rs == SG_OK)
+        rs = c->fail(SG_EDEVICE, "step: join of the gravity stream failed");
+    if (rs != SG_OK) return rs;
+    do_combine(c);
+    c->accel_after_predict = true;
+    if ((r = c->check_launch("combine")) != SG_OK) return r;
     return do_kick_drift(c, dt, SG_CORRECT);
 }
 
@@ -550,6 +581,17 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
     c->L = L;
     c->ws = (char*)d_workspace;
     c->st = (hipStream_t)stream;
+    c->st2 = nullptr;
+    c->ev_fork = c->ev_join = nullptr;
+    if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        // without them, steps run their two chains one after the other
+        if (c->st2) (void)hipStreamDestroy(c->st2);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        c->st2 = nullptr;
+        c->ev_fork = c->ev_join = nullptr;
+    }
     c->bound = false;
     c->ng = c->nh = c->n = 0;
     memset(&c->s, 0, sizeof(c->s));
@@ -569,6 +611,9 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
     sg_launch_grid_reset(c->grid(), c->st);
     if (c->check_launch("create") != SG_OK) {
         snprintf(g_create_msg, sizeof(g_create_msg), "%s", c->msg);
+        if (c->st2) (void)hipStreamDestroy(c->st2);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
         delete c;
         return SG_EDEVICE;
     }
@@ -799,7 +844,7 @@ sg_status sg_sync(sg_ctx* c, int64_t need[2]) {
     sg_launch_status_clear(c->grid(), c->st);
     (void)hipStreamSynchronize(c->st);
     c->invalidate_positions();
-    if (g.err & SGE_NONFINITE)
+    if (g.err & (SGE_NONFINITE | SGE_GNONFINITE))
         return c->fail(SG_ENONFINITE, "non-finite position or smoothing length <= 0");
     if (g.err & SGE_LEVELS)
         return c->fail(SG_ERANGE, "smoothing lengths span more than SG_MAX_LEVELS levels");
@@ -851,13 +896,17 @@ size_t ens_layout(int32_t nsys, int64_t ntasks, size_t* o_tasks, size_t* o_count
 // Run fn(c) for every system: system k on side stream k mod K, all side
 // streams forked from the shared stream and joined back into it (also while
 // the shared stream is being captured into a graph: the side streams then
-// join the capture).  Without side streams, in order on the shared stream.
-template <typename F>
-sg_status ens_each(sg_ens* e, F&& fn) {
+// join the capture).  shared() enqueues work on the shared stream right
+// after the fork, so that it runs beside the systems' work.  Without side
+// streams, everything in order on the shared stream.
+template <typename S, typename F>
+sg_status ens_fork_join(sg_ens* e, S&& shared, F&& fn) {
     const int K = (int)e->side.size();
     if (K == 0) {
+        sg_status r = shared();
+        if (r != SG_OK) return r;
         for (sg_ctx* c : e->c) {
-            const sg_status r = fn(c);
+            r = fn(c);
             if (r != SG_OK) return e->fail(r, c->msg);
         }
         return SG_OK;
@@ -866,8 +915,9 @@ sg_status ens_each(sg_ens* e, F&& fn) {
     for (int i = 0; i < K; ++i)
         if (hipStreamWaitEvent(e->side[i], e->ev[0], 0) != hipSuccess)
             return e->fail(SG_EDEVICE, "fork: stream wait failed");
-    sg_status rc = SG_OK;
+    sg_status rc = shared();
     char why[256] = "";
+    if (rc != SG_OK) snprintf(why, sizeof(why), "%s", e->msg);
     for (size_t k = 0; k < e->c.size() && rc == SG_OK; ++k) {
         sg_ctx* c = e->c[k];
         hipStream_t own = c->st;
@@ -888,13 +938,20 @@ sg_status ens_each(sg_ens* e, F&& fn) {
     return rc == SG_OK ? SG_OK : e->fail(rc, why);
 }
 
-sg_status ens_gravity(sg_ens* e, bool pot) {
-    sg_status r = ens_each(e, [&](sg_ctx* c) {
-        sg_grav_args a;
-        grav_args(c, pot, a);
-        return grav_prep(c, a);
-    });
-    if (r != SG_OK) return r;
+template <typename F>
+sg_status ens_each(sg_ens* e, F&& fn) {
+    return ens_fork_join(e, [] { return SG_OK; }, fn);
+}
+
+// Morton order, sorted copies and boxes of one system (its gravity inputs).
+sg_status ens_grav_prep(sg_ctx* c, bool pot) {
+    sg_grav_args a;
+    grav_args(c, pot, a);
+    return grav_prep(c, a);
+}
+
+// The batched gravity launch on the shared stream (inputs prepared).
+sg_status ens_grav_launch(sg_ens* e, bool pot) {
     sg_ctx* c0 = e->c[0];
     c0->begin(SG_ST_GRAV);
     sg_launch_grav_ensemble(e->d_sys, e->d_tasks, e->ntasks, e->d_counter, pot ? 1 : 0, e->eps,
@@ -907,6 +964,11 @@ sg_status ens_gravity(sg_ens* e, bool pot) {
         c->have_pot = pot;
     }
     return SG_OK;
+}
+
+sg_status ens_gravity(sg_ens* e, bool pot) {
+    sg_status r = ens_each(e, [&](sg_ctx* c) { return ens_grav_prep(c, pot); });
+    return r != SG_OK ? r : ens_grav_launch(e, pot);
 }
 
 sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
@@ -922,19 +984,26 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
         need_grav |= !c->have_grav || (pot && !c->have_pot);
     }
     if (need_grav && (r = ens_gravity(e, pot)) != SG_OK) return r;
+    // predictor, then each system's gravity inputs at the predicted positions
     r = ens_each(e, [&](sg_ctx* c) {
         sg_status q;
         if ((q = do_sph(c)) != SG_OK) return q;
         do_combine(c);
         if ((q = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return q;
-        if ((q = do_build(c)) != SG_OK) return q;
-        return do_density(c);
+        return ens_grav_prep(c, pot);
     });
     if (r != SG_OK) return r;
-    if ((r = ens_gravity(e, pot)) != SG_OK) return r;
-    return ens_each(e, [&](sg_ctx* c) {
+    // the batched gravity on the shared stream beside every system's
+    // neighbour build, density and corrector SPH forces on the side streams
+    // (disjoint buffers; the gravity kernel reads only the prepared inputs)
+    r = ens_fork_join(e, [&] { return ens_grav_launch(e, pot); }, [&](sg_ctx* c) {
         sg_status q;
-        if ((q = do_sph(c)) != SG_OK) return q;
+        if ((q = do_build(c)) != SG_OK) return q;
+        if ((q = do_density(c)) != SG_OK) return q;
+        return do_sph(c);
+    });
+    if (r != SG_OK) return r;
+    return ens_each(e, [&](sg_ctx* c) {
         do_combine(c);
         c->accel_after_predict = true;
         return do_kick_drift(c, dt, SG_CORRECT);
@@ -1145,6 +1214,12 @@ sg_status sg_profile_read(sg_ctx* c, double ms[SG_NSTAGE], int64_t count[SG_NSTA
 void sg_destroy(sg_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
+    if (c->st2) {
+        (void)hipStreamSynchronize(c->st2);
+        (void)hipStreamDestroy(c->st2);
+        (void)hipEventDestroy(c->ev_fork);
+        (void)hipEventDestroy(c->ev_join);
+    }
     for (auto& mk : c->marks) {
         (void)hipEventDestroy(mk.a);
         (void)hipEventDestroy(mk.b);

@@ -408,9 +408,11 @@ __global__ __launch_bounds__(kBlock) void k_grav_f32c_ens(const sg_ens_sys* __re
     for (;;) {
         if (threadIdx.x == 0) s_task = atomicAdd(counter, 1);
         __syncthreads();
-        const int32_t t = s_task;
+        // uniform: the task record and the system's pointers load into
+        // scalar registers
+        const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
         __syncthreads();
-        if (t >= ntasks) break;                  // uniform: every wavefront leaves here
+        if (t >= ntasks) break;                  // every wavefront leaves here
         const sg_ens_task tk = tasks[t];
         const sg_ens_sys S = sys[tk.sys];
         f32c_task<IPL, TILE, POT>(L, S.xs, S.ys, S.zs, S.ms, (const box6*)S.sbox, S.order, S.n,

@@ -15,11 +15,16 @@ enum : uint32_t {
     SGE_NNZ = 4u,         // neighbour pairs > nnz_cap
     SGE_NONFINITE = 8u,   // non-finite position, h <= 0 or non-finite h
     SGE_GRID = 16u,       // a level's cell count does not fit in int32
+    SGE_GNONFINITE = 32u, // non-finite position met by the gravity preparation
+                          // (apart from SGE_NONFINITE, which the neighbour
+                          // build reads: the two chains may run concurrently)
 };
 #define SGE_SORT_FATAL (SGE_LEVELS | SGE_CELLS | SGE_NONFINITE | SGE_GRID)
 
 // Grid of smoothing-length levels plus the device status word.  Lives in
-// the workspace; written only by device code during a neighbour build.
+// the workspace; written only by device code: the level fields by the
+// neighbour build, the gravity-order box (glo, ghi) by the gravity
+// preparation, the status word by both (atomic OR).
 // Workgroups of a launch are dealt to the 8 XCDs of the chip round-robin,
 // and each XCD has its own L2.  Kernels whose neighbouring targets share
 // data (neighbour gathers over slot-ordered particles) remap the block

@@ -182,10 +182,7 @@ __global__ void k_grid_reset(sg_grid_dev* g) {
         g->npart[t] = 0ull;
         g->ncell[t] = 0;
     }
-    if (t < 3) {
-        g->glo[t] = ~0ull;
-        g->ghi[t] = 0ull;
-    }
+    // glo / ghi belong to the gravity preparation, which resets them itself
 }
 
 // Minimum h and validity of the gas state.
@@ -481,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_gbox(const double* __restrict__ x,
             atomicMax(&g->ghi[d], b);
         }
     }
-    if (bad) atomicOr(&g->err, SGE_NONFINITE);
+    if (bad) atomicOr(&g->err, SGE_GNONFINITE);
 }
 
 __device__ inline uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
