@@ -94,7 +94,12 @@ typedef enum {
  *   L0 the smallest power of two >= (2 + 2^-9) min h); level-l cells get the
  *   side L0 * 2^(l + cell_scale_log2).  It changes cell keys, counts,
  *   offsets and the slot order (so the exported grid arrays and the order
- *   of SPH sums), never which particles are neighbours. */
+ *   of SPH sums), never which particles are neighbours.
+ * step_serial: 0 = in a step, gravity runs on the context's second stream
+ *   beside the neighbours -> density -> SPH(corrector) chain (default);
+ *   1 = the two one after the other on the context's stream (for kernel
+ *   traces whose per-kernel durations should not include waiting beside
+ *   the gravity kernel).  Results are the same either way, bit for bit. */
 typedef struct {
     double G, eps, gamma, alpha, beta, eta;
     int32_t precision;
@@ -103,7 +108,8 @@ typedef struct {
     int32_t grav_variant;
     int32_t grav_tile;
     int32_t cell_scale_log2;
-    int32_t reserved[2];        /* must be zero */
+    int32_t step_serial;
+    int32_t reserved[1];        /* must be zero */
 } sg_params;
 
 /* Capacities the workspace is sized for.

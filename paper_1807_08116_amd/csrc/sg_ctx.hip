@@ -136,6 +136,8 @@ bool params_ok(const sg_params* p, const char** why) {
     const int v = resolved_variant(*p);
     if ((p->precision == SG_FP32C || v == 1 || v == 3) && !(p->eps * p->eps >= 1.2e-38))
         return *why = "FP32 pair arithmetic needs eps^2 in the FP32 normal range", false;
+    if (p->step_serial != 0 && p->step_serial != 1)
+        return *why = "step_serial must be 0 or 1", false;
     for (int r : p->reserved)
         if (r != 0) return *why = "reserved fields must be zero", false;
     return true;
@@ -509,7 +511,7 @@ sg_status do_step(sg_ctx* c, double dt, uint32_t flags) {
     // the context's stream, also while it is being captured) and the chain
     // on the context's stream.  They touch disjoint workspace buffers and
     // disjoint fields of the grid record (the status word by atomic OR).
-    if (!c->st2) {
+    if (!c->st2 || c->prm.step_serial) {
         if ((r = do_build(c)) != SG_OK) return r;
         if ((r = do_density(c)) != SG_OK) return r;
         if ((r = do_accel(c, gflags | SG_SPH)) != SG_OK) return r;
@@ -995,13 +997,21 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
     if (r != SG_OK) return r;
     // the batched gravity on the shared stream beside every system's
     // neighbour build, density and corrector SPH forces on the side streams
-    // (disjoint buffers; the gravity kernel reads only the prepared inputs)
-    r = ens_fork_join(e, [&] { return ens_grav_launch(e, pot); }, [&](sg_ctx* c) {
+    // (disjoint buffers; the gravity kernel reads only the prepared inputs),
+    // or before them with step_serial (of the first context)
+    auto chain = [&](sg_ctx* c) {
         sg_status q;
         if ((q = do_build(c)) != SG_OK) return q;
         if ((q = do_density(c)) != SG_OK) return q;
         return do_sph(c);
-    });
+    };
+    auto launch = [&] { return ens_grav_launch(e, pot); };
+    if (e->c[0]->prm.step_serial) {
+        if ((r = launch()) != SG_OK) return r;
+        r = ens_each(e, chain);
+    } else {
+        r = ens_fork_join(e, launch, chain);
+    }
     if (r != SG_OK) return r;
     return ens_each(e, [&](sg_ctx* c) {
         do_combine(c);

@@ -60,14 +60,15 @@ def test_workspace_validation(sg):
                 dict(grav_variant=1, eps=1e-20),
                 dict(precision=1, grav_variant=2), dict(precision=1, eps=1e-20),
                 dict(grav_tile=64), dict(grav_tile=1024), dict(cell_scale_log2=2),
-                dict(cell_scale_log2=-2)):
+                dict(cell_scale_log2=-2), dict(step_serial=2), dict(step_serial=-1)):
         assert sg.workspace_bytes(sg.make_params(**bad), caps) == 0, bad
     for ok in (dict(grav_tile=128), dict(grav_tile=512), dict(cell_scale_log2=-1),
                dict(cell_scale_log2=1), dict(grav_variant=2, eps=1e-20),
-               dict(grav_variant=3), dict(grav_variant=4, eps=1e-20), dict(eps=1e-20)):
+               dict(grav_variant=3), dict(grav_variant=4, eps=1e-20), dict(eps=1e-20),
+               dict(step_serial=1)):
         assert sg.workspace_bytes(sg.make_params(**ok), caps) > 0, ok
     p = sg.make_params()
-    p.reserved[1] = 1
+    p.reserved[0] = 1
     assert sg.workspace_bytes(p, caps) == 0
     assert sg.workspace_bytes(good, sg.Caps(0, 0, 0, 0)) == 0
     assert sg.workspace_bytes(good, sg.Caps(-1, 5, 5, 5)) == 0

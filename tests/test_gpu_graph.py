@@ -105,3 +105,34 @@ def test_checkpoint_resume_bitwise(sg, c0, form):
         resumed.ctx.step(dt, sg.SG_POT)
     for f in ("x", "y", "z", "vx", "vy", "vz", "e", "ax", "pot"):
         np.testing.assert_array_equal(resumed.numpy(f), straight.numpy(f), err_msg=f)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+def test_overlapped_steps_equal_serial(sg, c0, form):
+    # gravity beside the neighbour/SPH chain (default) and after it
+    # (step_serial) give the same trajectory bit for bit, eager and captured
+    p = sg.SG_FP32C if form == "fp32c" else sg.SG_FP64
+    runs = []
+    for serial in (0, 1):
+        for graph in (False, True):
+            eng = sg.Engine(c0, precision=p, step_serial=serial, stream="new")
+            eng.ctx.run(1e-3, 4, sg.SG_POT, use_graph=graph)
+            runs.append({f: eng.numpy(f) for f in FIELDS})
+            eng.ctx.close()
+    for r in runs[1:]:
+        for f in FIELDS:
+            np.testing.assert_array_equal(r[f], runs[0][f], err_msg=f)
+
+
+def test_ensemble_overlapped_steps_equal_serial(sg):
+    from paper_1807_08116_amd import ic
+    states = ic.ensemble(nsys=4, scale=0.03)
+    out = []
+    for serial in (0, 1):
+        ens = sg.Ensemble(states, step_serial=serial)
+        ens.run(1e-3, 3, sg.SG_POT, use_graph=True)
+        out.append([{f: e.numpy(f) for f in FIELDS} for e in ens.engines])
+        ens.close()
+    for a, b in zip(*out):
+        for f in FIELDS:
+            np.testing.assert_array_equal(a[f], b[f], err_msg=f)
