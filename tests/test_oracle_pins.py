@@ -294,6 +294,43 @@ def test_sph_conservation_laws(orc):
     np.testing.assert_allclose(de2, de, rtol=1e-9, atol=1e-12 * np.abs(de).max())
 
 
+def test_two_particle_sph_closed_form(orc):
+    # Two gas particles on the x axis at -1/2 and +1/2 with h = m = e = 1,
+    # gamma = 5/3, alpha = 1, beta = 2, eta = 0.1, worked by hand from the
+    # density sum (self term included), the ideal-gas law, the viscosity
+    # (mu with r^2 + eta h^2 in the denominator, as printed), the momentum
+    # and energy equations (Sec. 2.2), with xi = 1:
+    #   W(0) = 1/pi, W(1) = 1/(4 pi)  ->  rho = 5/(4 pi), p = 5/(6 pi),
+    #   p/rho^2 = 8 pi/15, c = sqrt(gamma (gamma - 1) e) = sqrt(10)/3,
+    #   grad_i W_p = -(45/(64 pi)) r_ij/|r_ij| = +45/(64 pi) x  (r_ij = -x).
+    # Receding (v_i = -1/4, v_j = +1/4): no viscosity, Pi = 16 pi/15, so
+    #   a_i = -Pi 45/(64 pi) = -3/4 and de_i/dt = Pi (v_ij . grad W)/2 = -3/16.
+    # Approaching (v_i = +1/4, v_j = -1/4): mu = -0.5/1.1 = -5/11 and
+    #   nu = mu (beta mu - alpha c)/rho = (4 pi/11)(10/11 + sqrt(10)/3).
+    x = np.array([-0.5, 0.5]); y = np.zeros(2); z = np.zeros(2)
+    m = np.ones(2); h = np.ones(2); e = np.ones(2)
+    off = np.array([0, 1, 2], dtype=np.int64); idx = np.array([1, 0], dtype=np.int32)
+    rho = orc.density(x, y, z, m, h, off, idx)
+    np.testing.assert_allclose(rho, 5 / (4 * PI), rtol=1e-15)
+    p, c = orc.eos(rho, e, 5 / 3)
+    np.testing.assert_allclose(p / rho ** 2, 8 * PI / 15, rtol=1e-14)
+    np.testing.assert_allclose(c, math.sqrt(10) / 3, rtol=1e-14)
+    zero = np.zeros(2)
+
+    def force(v):
+        return orc.sph_force(x, y, z, np.array([v, -v]), zero, zero, m, h, rho, e,
+                             5 / 3, 1.0, 2.0, 0.1, off, idx)
+    ax, ay, az, de = force(-0.25)
+    np.testing.assert_allclose(ax, [-0.75, 0.75], rtol=1e-14)
+    np.testing.assert_allclose(de, [-3 / 16, -3 / 16], rtol=1e-14)
+    assert np.all(ay == 0) and np.all(az == 0)
+    ax, ay, az, de = force(0.25)
+    Pi = 16 * PI / 15 + (4 * PI / 11) * (10 / 11 + math.sqrt(10) / 3)
+    g = 45 / (64 * PI)
+    np.testing.assert_allclose(ax, [-g * Pi, g * Pi], rtol=1e-14)
+    np.testing.assert_allclose(de, [0.25 * g * Pi, 0.25 * g * Pi], rtol=1e-14)
+
+
 def test_viscosity_scaling(orc):
     # nu = mu (beta mu - alpha c)/rho_ij: the alpha part of the heating is
     # linear in alpha and the beta part scales as |v|^3 (mu ~ v, mu^2 dv ~ v^3).
