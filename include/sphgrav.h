@@ -279,8 +279,8 @@ sg_status sg_sync(sg_ctx *ctx, int64_t need[2]);
  * the same G, eps and stream).  Gravity of all systems runs as ONE
  * persistent launch: workgroups take (system, block of 256 * grav_ipl
  * targets) tasks, largest systems first, from a device counter until none
- * is left; grav_ipl and grav_tile (resolved as for sg_compute_accel) are
- * those of the first context.
+ * is left; grav_ipl and grav_tile are those of the first context, 0
+ * selecting 2 targets per lane and 512 sources per tile for this launch.
  * The ensemble keeps pointers into the contexts: do not rebind or destroy
  * them while it exists.  d_ws: caller-owned device memory of
  * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task
@@ -295,8 +295,13 @@ sg_status sg_ensemble_gravity(sg_ens *e, uint32_t flags);
 /* One predictor-corrector step of every system (as sg_step), gravity batched.
  * The systems' own launches run on up to 8 side streams of the ensemble
  * (default priority) forked from and joined back into the shared stream;
- * after SG_PREDICT the batched gravity runs on the shared stream beside
- * the systems' neighbours -> density -> SPH(corrector) chains. */
+ * after SG_PREDICT the batched gravity runs beside the systems'
+ * neighbours -> density -> SPH(corrector) chains, on a stream of its own
+ * (created by sg_ensemble_create with every CU in its mask, so that it
+ * holds a hardware queue of its own; the shared stream if that creation
+ * fails), forked from the shared stream and joined back into it after the
+ * chains are enqueued.  With step_serial (of the first context) the
+ * gravity runs on the shared stream before the chains. */
 sg_status sg_ensemble_step(sg_ens *e, double dt, uint32_t flags);
 /* nsteps ensemble steps; with use_graph the steady-state step is captured
  * once and replayed (as sg_run).  Waits for the stream. */

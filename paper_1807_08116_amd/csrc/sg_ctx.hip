@@ -175,6 +175,7 @@ struct sg_ctx {
     bool have_nbr, have_rho, have_grav, have_pot, have_sph;
     bool predicted;        // between SG_PREDICT and SG_CORRECT
     bool accel_after_predict;
+    bool beside_grav;      // launches being enqueued share the GPU with the gravity kernel
     char msg[256];
     // stage timing
     bool prof;
@@ -246,6 +247,7 @@ struct sg_ctx {
         b.perm = at<int32_t>(L.perm);
         b.nbr_off = at<int64_t>(L.nbr_off);
         b.nbr_idx = at<int32_t>(L.nbr_idx);
+        b.beside_grav = beside_grav ? 1 : 0;
         return b;
     }
     void invalidate_positions() {
@@ -524,9 +526,11 @@ sg_status do_step(sg_ctx* c, double dt, uint32_t flags) {
     c->st = c->st2;
     sg_status rg = do_gravity(c, (flags & SG_POT) != 0);
     c->st = own;
+    c->beside_grav = true;
     sg_status rs = rg != SG_OK ? rg : do_build(c);
     if (rs == SG_OK) rs = do_density(c);
     if (rs == SG_OK) rs = do_sph(c);
+    c->beside_grav = false;
     // join (also after an error, so that a capture stays whole)
     if ((hipEventRecord(c->ev_join, c->st2) != hipSuccess ||
          hipStreamWaitEvent(c->st, c->ev_join, 0) != hipSuccess) && rs == SG_OK)
@@ -865,6 +869,10 @@ struct sg_ens {
     // side by side, forked from and joined back into st with events
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> ev;
+    // the batched gravity kernel's own stream (all CUs in its mask, which
+    // gives it a hardware queue of its own) with its fork/join events
+    hipStream_t gst;
+    hipEvent_t gev[2];
     sg_ens_sys* d_sys;
     sg_ens_task* d_tasks;
     int32_t* d_counter;
@@ -880,6 +888,9 @@ struct sg_ens {
         if (st) (void)hipStreamSynchronize(st);
         for (hipStream_t x : side) (void)hipStreamDestroy(x);
         for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+        if (gst) (void)hipStreamDestroy(gst);
+        for (hipEvent_t x : gev)
+            if (x) (void)hipEventDestroy(x);
     }
 };
 
@@ -952,13 +963,17 @@ sg_status ens_grav_prep(sg_ctx* c, bool pot) {
     return grav_prep(c, a);
 }
 
-// The batched gravity launch on the shared stream (inputs prepared).
-sg_status ens_grav_launch(sg_ens* e, bool pot) {
+// The batched gravity launch on stream st (inputs prepared; stage timing
+// is recorded on st through the first context).
+sg_status ens_grav_launch(sg_ens* e, bool pot, hipStream_t st) {
     sg_ctx* c0 = e->c[0];
+    hipStream_t own = c0->st;
+    c0->st = st;
     c0->begin(SG_ST_GRAV);
     sg_launch_grav_ensemble(e->d_sys, e->d_tasks, e->ntasks, e->d_counter, pot ? 1 : 0, e->eps,
-                            e->G, e->ipl, e->tile, e->nblocks, e->st);
+                            e->G, e->ipl, e->tile, e->nblocks, st);
     c0->end();
+    c0->st = own;
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return e->fail(SG_EDEVICE, hipGetErrorString(err));
     for (sg_ctx* c : e->c) {
@@ -970,7 +985,7 @@ sg_status ens_grav_launch(sg_ens* e, bool pot) {
 
 sg_status ens_gravity(sg_ens* e, bool pot) {
     sg_status r = ens_each(e, [&](sg_ctx* c) { return ens_grav_prep(c, pot); });
-    return r != SG_OK ? r : ens_grav_launch(e, pot);
+    return r != SG_OK ? r : ens_grav_launch(e, pot, e->st);
 }
 
 sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
@@ -1000,17 +1015,35 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
     // (disjoint buffers; the gravity kernel reads only the prepared inputs),
     // or before them with step_serial (of the first context)
     auto chain = [&](sg_ctx* c) {
-        sg_status q;
-        if ((q = do_build(c)) != SG_OK) return q;
-        if ((q = do_density(c)) != SG_OK) return q;
-        return do_sph(c);
+        c->beside_grav = !e->c[0]->prm.step_serial;
+        sg_status q = do_build(c);
+        if (q == SG_OK) q = do_density(c);
+        if (q == SG_OK) q = do_sph(c);
+        c->beside_grav = false;
+        return q;
     };
-    auto launch = [&] { return ens_grav_launch(e, pot); };
     if (e->c[0]->prm.step_serial) {
-        if ((r = launch()) != SG_OK) return r;
+        if ((r = ens_grav_launch(e, pot, e->st)) != SG_OK) return r;
         r = ens_each(e, chain);
+    } else if (!e->gst) {
+        r = ens_fork_join(e, [&] { return ens_grav_launch(e, pot, e->st); }, chain);
     } else {
+        // gravity on its own stream and hardware queue, joined back only
+        // after every chain is enqueued: a hardware queue runs its packets
+        // in order, so neither the kernel nor a wait for it may sit ahead
+        // of a chain's launches in a queue that a side stream shares
+        bool forked = false;
+        auto launch = [&] {
+            if (hipEventRecord(e->gev[0], e->st) != hipSuccess ||
+                hipStreamWaitEvent(e->gst, e->gev[0], 0) != hipSuccess)
+                return e->fail(SG_EDEVICE, "fork to the gravity stream failed");
+            forked = true;
+            return ens_grav_launch(e, pot, e->gst);
+        };
         r = ens_fork_join(e, launch, chain);
+        if (forked && (hipEventRecord(e->gev[1], e->gst) != hipSuccess ||
+                       hipStreamWaitEvent(e->st, e->gev[1], 0) != hipSuccess) && r == SG_OK)
+            r = e->fail(SG_EDEVICE, "join of the gravity stream failed");
     }
     if (r != SG_OK) return r;
     return ens_each(e, [&](sg_ctx* c) {
@@ -1038,10 +1071,13 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
     std::vector<std::pair<int64_t, sg_ens_task>> tasks;
     int64_t total = 0;
     if (!ctxs[0] || !ctxs[0]->bound) return SG_EINVAL;
-    // launch shape of the first context: 256 * ipl targets per task
-    const int ipl = ctxs[0]->prm.grav_ipl != 0 ? ctxs[0]->prm.grav_ipl
-                                               : auto_ipl(SG_FP32C, ctxs[0]->n);
-    const int tile = resolved_tile(ctxs[0]->prm);
+    // launch shape of the first context: 256 * ipl targets per task.  Unset
+    // fields take the batched launch's measured best at 64 systems of
+    // 8192-262144 particles, 2 targets per lane and 512 sources per tile
+    // (the tasks fill the GPU whatever the systems' sizes, so the choice
+    // does not follow the single-system rule).
+    const int ipl = ctxs[0]->prm.grav_ipl != 0 ? ctxs[0]->prm.grav_ipl : 2;
+    const int tile = ctxs[0]->prm.grav_tile != 0 ? ctxs[0]->prm.grav_tile : 512;
     const int64_t per = 256 * (int64_t)ipl;
     for (int32_t k = 0; k < nsys; ++k) {
         sg_ctx* c = ctxs[k];
@@ -1104,6 +1140,20 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
         for (hipEvent_t x : e->ev) (void)hipEventDestroy(x);
         e->side.clear();
         e->ev.clear();
+    }
+    if (!e->side.empty()) {
+        std::vector<uint32_t> mask((size_t)((cus > 0 ? cus : 256) + 31) / 32, 0xffffffffu);
+        if (cus > 0 && cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
+        if (hipExtStreamCreateWithCUMask(&e->gst, (uint32_t)mask.size(), mask.data()) != hipSuccess ||
+            hipEventCreateWithFlags(&e->gev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&e->gev[1], hipEventDisableTiming) != hipSuccess) {
+            if (e->gst) (void)hipStreamDestroy(e->gst);   // fall back: gravity on st
+            e->gst = nullptr;
+            for (hipEvent_t& x : e->gev) {
+                if (x) (void)hipEventDestroy(x);
+                x = nullptr;
+            }
+        }
     }
     // persistent grid: as many workgroups as are resident at once
     const int per_cu = sg_grav_ensemble_blocks_per_cu(ipl, tile, 1);

@@ -136,6 +136,7 @@ struct sg_sph_bufs {
     const int32_t* perm;
     const int64_t* nbr_off;
     const int32_t* nbr_idx;
+    int beside_grav;                    // 1: the launch shares the GPU with the gravity kernel
 };
 void sg_launch_density(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
                        double* rho_out, hipStream_t st);

@@ -71,29 +71,40 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t* __restric
 }
 
 // Single block: exclusive scan of the block sums in place; out[n] = total.
-__global__ __launch_bounds__(1024) void k_scan_bsums(int64_t* __restrict__ bsum, int64_t n_host,
-                                                     const int64_t* __restrict__ n_dev,
-                                                     int64_t cap, int64_t* __restrict__ out) {
+// 256 threads, 4 sums each per pass: one wavefront per SIMD, so the block
+// also finds room on CUs that another kernel's workgroups mostly fill.
+__global__ __launch_bounds__(256) void k_scan_bsums(int64_t* __restrict__ bsum, int64_t n_host,
+                                                    const int64_t* __restrict__ n_dev,
+                                                    int64_t cap, int64_t* __restrict__ out) {
     const int64_t n = scan_n(n_host, n_dev, cap);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    __shared__ int64_t buf[1024];
+    __shared__ int64_t buf[256];
     __shared__ int64_t carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
-        int64_t i = c0 + threadIdx.x;
-        int64_t v = i < nb ? bsum[i] : 0;
-        buf[threadIdx.x] = v;
+        const int64_t i0 = c0 + 4 * (int64_t)threadIdx.x;
+        int64_t v[4];
+        int64_t tsum = 0;
+        for (int k = 0; k < 4; ++k) {
+            v[k] = i0 + k < nb ? bsum[i0 + k] : 0;
+            tsum += v[k];
+        }
+        buf[threadIdx.x] = tsum;
         __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {      // Hillis-Steele inclusive scan
+        for (int o = 1; o < 256; o <<= 1) {       // Hillis-Steele inclusive scan
             int64_t t = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0;
             __syncthreads();
             buf[threadIdx.x] += t;
             __syncthreads();
         }
-        if (i < nb) bsum[i] = carry + buf[threadIdx.x] - v;
+        int64_t run = carry + buf[threadIdx.x] - tsum;
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < nb) bsum[i0 + k] = run;
+            run += v[k];
+        }
         __syncthreads();
-        if (threadIdx.x == 0) carry += buf[1023];
+        if (threadIdx.x == 0) carry += buf[255];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[n] = carry;
@@ -597,7 +608,7 @@ void sg_launch_scan(const int32_t* in, int64_t* out, int64_t n_host, const int64
     const unsigned nb = grid_for(cap, kScanTile);
     int64_t* bsum = (int64_t*)tmp;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, st, in, n_host, n_dev, cap, bsum);
-    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(1024), 0, st, bsum, n_host, n_dev, cap, out);
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(256), 0, st, bsum, n_host, n_dev, cap, out);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, st, in, out, n_host, n_dev, cap,
                        bsum);
 }

@@ -26,7 +26,12 @@ constexpr double kPi = 3.14159265358979323846;
 // that at most 2 workgroups share a CU (160 KB of LDS per CU): measured at
 // 2M particles, density 0.91 -> 0.51 ms and the force pass 1.11 -> 0.85 ms
 // (FP32C), 1.27 -> 1.08 ms (FP64); 1 or 3 workgroups per CU were slower.
+// A pass that runs beside the gravity kernel reserves nothing: the gravity
+// workgroups hold most of every CU's LDS, so an 80 KB request would keep
+// the pass off the GPU until the gravity kernel drains.
 constexpr unsigned kGatherLds = 80 * 1024;
+
+inline unsigned gather_lds(const sg_sph_bufs& b) { return b.beside_grav ? 0u : kGatherLds; }
 
 inline unsigned grid_for(int64_t n) {
     int64_t b = (n + kBlock - 1) / kBlock;
@@ -297,9 +302,9 @@ __global__ __launch_bounds__(kBlock) void k_update_h(sg_sph_bufs b, const sg_gri
 void sg_launch_density(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
                        double* rho_out, hipStream_t st) {
     if (precision == SG_FP32C)
-        hipLaunchKernelGGL(k_density_f32, dim3(grid_for(ng)), dim3(kBlock), kGatherLds, st, b, g, ng, rho_out);
+        hipLaunchKernelGGL(k_density_f32, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng, rho_out);
     else
-        hipLaunchKernelGGL(k_density_f64, dim3(grid_for(ng)), dim3(kBlock), kGatherLds, st, b, g, ng, rho_out);
+        hipLaunchKernelGGL(k_density_f64, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng, rho_out);
 }
 
 void sg_launch_sph_prep(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
@@ -313,10 +318,10 @@ void sg_launch_sph_force(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng,
                          double alpha, double beta, double eta, double* asx, double* asy,
                          double* asz, double* dedt, hipStream_t st) {
     if (precision == SG_FP32C)
-        hipLaunchKernelGGL(k_sph_force_f32, dim3(grid_for(ng)), dim3(kBlock), kGatherLds, st, b, g, ng,
+        hipLaunchKernelGGL(k_sph_force_f32, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng,
                            (float)alpha, (float)beta, (float)eta, asx, asy, asz, dedt);
     else
-        hipLaunchKernelGGL(k_sph_force_f64, dim3(grid_for(ng)), dim3(kBlock), kGatherLds, st, b, g, ng,
+        hipLaunchKernelGGL(k_sph_force_f64, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng,
                            alpha, beta, eta, asx, asy, asz, dedt);
 }
 

@@ -57,7 +57,8 @@ def test_ensemble_steps_match_single_and_graph(sg, states):
     graph = sg.Ensemble(states, grav_ipl=2)
     graph.run(dt, 4, sg.SG_POT, use_graph=True)
     for st, e1, e2 in zip(states, eager.engines, graph.engines):
-        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_ipl=2)
+        # the batched launch's automatic tile is 512 sources
+        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_ipl=2, grav_tile=512)
         for _ in range(4):
             single.ctx.step(dt, sg.SG_POT)
         single.ctx.sync()
