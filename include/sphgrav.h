@@ -99,7 +99,16 @@ typedef enum {
  *   beside the neighbours -> density -> SPH(corrector) chain (default);
  *   1 = the two one after the other on the context's stream (for kernel
  *   traces whose per-kernel durations should not include waiting beside
- *   the gravity kernel).  Results are the same either way, bit for bit. */
+ *   the gravity kernel).  Results are the same either way, bit for bit.
+ * grav_reorder: gravity preparations per recomputation of the Morton order
+ *   that the SG_FP32C and expanded-FP64 kernels visit particles in (0 or
+ *   1 = every preparation, at most 1024).  In between, the order is
+ *   reused: the sorted copies and the 64-particle boxes are still rebuilt
+ *   from the current positions, so the near/far choice and its error bound
+ *   hold for any order; a stale order only makes the boxes less compact
+ *   (more near-field pairs).  Results depend on the period at rounding
+ *   level (other groupings); runs with one period are reproducible bit
+ *   for bit, eager or graph-captured (sg_run, sg_ensemble_run). */
 typedef struct {
     double G, eps, gamma, alpha, beta, eta;
     int32_t precision;
@@ -109,7 +118,7 @@ typedef struct {
     int32_t grav_tile;
     int32_t cell_scale_log2;
     int32_t step_serial;
-    int32_t reserved[1];        /* must be zero */
+    int32_t grav_reorder;
 } sg_params;
 
 /* Capacities the workspace is sized for.
@@ -200,9 +209,11 @@ sg_status sg_step(sg_ctx *ctx, double dt, uint32_t flags);
 
 /* nsteps whole steps (as sg_step) with the conserved quantities of each
  * step written to d_hist[10*k .. 10*k+9] (device, may be NULL).  With
- * use_graph != 0, the first step runs eagerly and the steady-state step
- * (step + diagnostics) is captured once into a HIP graph and replayed for
- * the remaining steps (dt is fixed inside the graph; stage timing must be
+ * use_graph != 0, the first step runs eagerly, then P steady-state steps
+ * (step + diagnostics; P = grav_reorder when it is above 1 and the kernel
+ * uses the Morton order, else 1: one period of that order's schedule) are
+ * captured once into a HIP graph and replayed while P steps remain; the
+ * rest run eagerly (dt is fixed inside the graph; stage timing must be
  * off; the context's stream must not be the null stream, which cannot be
  * captured: SG_EINVAL before any work).  Results are identical to nsteps
  * calls of sg_step.  Waits for the stream before returning. */
@@ -276,11 +287,12 @@ sg_status sg_export(sg_ctx *ctx, int32_t what, void *d_dst, int64_t cap_bytes,
 sg_status sg_sync(sg_ctx *ctx, int64_t need[2]);
 
 /* Ensembles of independent systems (one bound context each, all SG_FP32C,
- * the same G, eps and stream).  Gravity of all systems runs as ONE
- * persistent launch: workgroups take (system, block of 256 * grav_ipl
- * targets) tasks, largest systems first, from a device counter until none
- * is left; grav_ipl and grav_tile are those of the first context, 0
- * selecting 2 targets per lane and 512 sources per tile for this launch.
+ * the same G, eps, grav_reorder and stream; SG_EINVAL otherwise).
+ * Gravity of all systems runs as ONE persistent launch: workgroups take
+ * (system, block of 256 * grav_ipl targets) tasks, largest systems first,
+ * from a device counter until none is left; grav_ipl and grav_tile are
+ * those of the first context, 0 selecting 2 targets per lane and 512
+ * sources per tile for this launch.
  * The ensemble keeps pointers into the contexts: do not rebind or destroy
  * them while it exists.  d_ws: caller-owned device memory of
  * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task
@@ -303,8 +315,8 @@ sg_status sg_ensemble_gravity(sg_ens *e, uint32_t flags);
  * chains are enqueued.  With step_serial (of the first context) the
  * gravity runs on the shared stream before the chains. */
 sg_status sg_ensemble_step(sg_ens *e, double dt, uint32_t flags);
-/* nsteps ensemble steps; with use_graph the steady-state step is captured
- * once and replayed (as sg_run).  Waits for the stream. */
+/* nsteps ensemble steps; with use_graph one period of steady-state steps
+ * is captured once and replayed (as sg_run).  Waits for the stream. */
 sg_status sg_ensemble_run(sg_ens *e, double dt, int64_t nsteps, uint32_t flags, int32_t use_graph);
 const char *sg_ensemble_last_error(const sg_ens *e);
 void sg_ensemble_destroy(sg_ens *e);

@@ -106,7 +106,8 @@ layout make_layout(const sg_params* p, const sg_caps* c) {
     L.vtz = take(8 * n);
     L.et = take(8 * ng);
     L.diag = take(sg_diag_tmp_bytes());
-    L.diag_out = take(10 * sizeof(double));
+    // per-step diagnostics of one captured chunk of steps (sg_run)
+    L.diag_out = take(10 * sizeof(double) * (size_t)(p->grav_reorder > 1 ? p->grav_reorder : 1));
     L.total = o;
     return L;
 }
@@ -138,8 +139,8 @@ bool params_ok(const sg_params* p, const char** why) {
         return *why = "FP32 pair arithmetic needs eps^2 in the FP32 normal range", false;
     if (p->step_serial != 0 && p->step_serial != 1)
         return *why = "step_serial must be 0 or 1", false;
-    for (int r : p->reserved)
-        if (r != 0) return *why = "reserved fields must be zero", false;
+    if (p->grav_reorder < 0 || p->grav_reorder > 1024)
+        return *why = "grav_reorder must be in [0, 1024]", false;
     return true;
 }
 
@@ -176,6 +177,10 @@ struct sg_ctx {
     bool predicted;        // between SG_PREDICT and SG_CORRECT
     bool accel_after_predict;
     bool beside_grav;      // launches being enqueued share the GPU with the gravity kernel
+    // Morton order of the gravity kernels: valid for the bound particles,
+    // and gravity preparations since it was computed
+    bool have_order;
+    int32_t order_age;
     char msg[256];
     // stage timing
     bool prof;
@@ -376,6 +381,17 @@ void grav_args(sg_ctx* c, bool pot, sg_grav_args& a) {
     a.gz = c->at<double>(c->L.gz);
     a.gpot = c->s.pot ? c->s.pot : c->at<double>(c->L.gpot);
     a.part = c->at<double>(c->L.part);
+    a.err = &c->grid()->err;
+}
+
+// Gravity preparations per Morton sort (1 when the kernel uses no order).
+int reorder_period(const sg_ctx* c) {
+    return uses_morton(c->prm) && c->prm.grav_reorder > 1 ? c->prm.grav_reorder : 1;
+}
+
+// The next gravity preparation recomputes the Morton order.
+bool sorts_next(const sg_ctx* c) {
+    return !c->have_order || c->order_age >= reorder_period(c);
 }
 
 // Morton order, sorted copies and 64-particle boxes at the current
@@ -383,8 +399,13 @@ void grav_args(sg_ctx* c, bool pot, sg_grav_args& a) {
 sg_status grav_prep(sg_ctx* c, const sg_grav_args& a) {
     if (!uses_morton(c->prm)) return SG_OK;
     c->begin(SG_ST_GRAV_PREP);
-    sg_launch_morton_order(c->s.x, c->s.y, c->s.z, c->n, c->grid(), const_cast<int32_t*>(a.order),
-                           c->at<void>(c->L.morton), c->st);
+    if (sorts_next(c)) {
+        sg_launch_morton_order(c->s.x, c->s.y, c->s.z, c->n, c->grid(),
+                               const_cast<int32_t*>(a.order), c->at<void>(c->L.morton), c->st);
+        c->have_order = true;
+        c->order_age = 0;
+    }
+    ++c->order_age;
     const int rc = sg_launch_grav_sorted(a, c->st);
     c->end();
     if (rc != 0) return c->fail(SG_EINVAL, "gravity preparation: missing buffer");
@@ -602,6 +623,7 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
     c->ng = c->nh = c->n = 0;
     memset(&c->s, 0, sizeof(c->s));
     c->invalidate_positions();
+    c->have_order = false;
     c->predicted = false;
     c->accel_after_predict = false;
     c->msg[0] = 0;
@@ -650,6 +672,7 @@ sg_status sg_bind_state(sg_ctx* c, int64_t n_gas, int64_t n_halo, const sg_state
     c->n = n_gas + n_halo;
     c->bound = true;
     c->invalidate_positions();
+    c->have_order = false;
     c->predicted = false;
     c->accel_after_predict = false;
     sg_launch_status_clear(c->grid(), c->st);
@@ -691,20 +714,34 @@ sg_status sg_run(sg_ctx* c, double dt, int64_t nsteps, uint32_t flags, int32_t u
     if (use_graph && nsteps >= 2 && c->st == nullptr)
         return c->fail(SG_EINVAL, "graph capture needs a stream other than the null stream");
     double* diag = c->at<double>(c->L.diag_out);
-    for (int64_t k = 0; k < nsteps; ++k) {
-        if (use_graph && k == 1) break;
-        if ((r = do_step(c, dt, flags)) != SG_OK) return r;
-        if (d_hist && (r = do_diag(c, d_hist + 10 * k)) != SG_OK) return r;
+    // A captured chunk holds one period of the Morton-order schedule (P
+    // steps, one recomputation each), so that its replays recompute the
+    // order exactly where eager steps would.
+    const int64_t P = reorder_period(c);
+    auto eager = [&](int64_t k) {
+        sg_status q = do_step(c, dt, flags);
+        if (q == SG_OK && d_hist) q = do_diag(c, d_hist + 10 * k);
+        return q;
+    };
+    int64_t k = 0;
+    const int64_t chunks = nsteps >= 1 ? (nsteps - 1) / P : 0;
+    if (!use_graph || chunks < 1) {
+        for (; k < nsteps; ++k)
+            if ((r = eager(k)) != SG_OK) return r;
+        return hipStreamSynchronize(c->st) == hipSuccess ? SG_OK
+                                                          : c->fail(SG_EDEVICE, "stream sync failed");
     }
-    if (!use_graph || nsteps < 2) return hipStreamSynchronize(c->st) == hipSuccess
-                                              ? SG_OK : c->fail(SG_EDEVICE, "stream sync failed");
-    // steady state reached: capture one step (+ diagnostics into a fixed slot)
+    // one eager step reaches the steady state (cached lists and forces)
+    if ((r = eager(k++)) != SG_OK) return r;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     if (hipStreamBeginCapture(c->st, hipStreamCaptureModeRelaxed) != hipSuccess)
         return c->fail(SG_EDEVICE, "hipStreamBeginCapture failed");
-    sg_status rc = do_step(c, dt, flags);
-    if (rc == SG_OK && d_hist) rc = do_diag(c, diag);
+    sg_status rc = SG_OK;
+    for (int64_t j = 0; j < P && rc == SG_OK; ++j) {
+        rc = do_step(c, dt, flags);
+        if (rc == SG_OK && d_hist) rc = do_diag(c, diag + 10 * j);
+    }
     hipError_t ec = hipStreamEndCapture(c->st, &graph);
     if (rc != SG_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -715,12 +752,13 @@ sg_status sg_run(sg_ctx* c, double dt, int64_t nsteps, uint32_t flags, int32_t u
         (void)hipGraphDestroy(graph);
         return c->fail(SG_EDEVICE, "hipGraphInstantiate failed");
     }
-    for (int64_t k = 1; k < nsteps && rc == SG_OK; ++k) {
+    for (int64_t q = 0; q < chunks && rc == SG_OK; ++q, k += P) {
         if (hipGraphLaunch(exec, c->st) != hipSuccess) rc = c->fail(SG_EDEVICE, "hipGraphLaunch failed");
-        else if (d_hist && hipMemcpyAsync(d_hist + 10 * k, diag, 10 * sizeof(double),
+        else if (d_hist && hipMemcpyAsync(d_hist + 10 * k, diag, 10 * sizeof(double) * (size_t)P,
                                           hipMemcpyDeviceToDevice, c->st) != hipSuccess)
             rc = c->fail(SG_EDEVICE, "history copy failed");
     }
+    for (; k < nsteps && rc == SG_OK; ++k) rc = eager(k);
     if (hipStreamSynchronize(c->st) != hipSuccess && rc == SG_OK)
         rc = c->fail(SG_EDEVICE, "stream sync failed");
     (void)hipGraphExecDestroy(exec);
@@ -1083,7 +1121,8 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
         sg_ctx* c = ctxs[k];
         if (!c || !c->bound) return SG_EINVAL;
         if (c->prm.precision != SG_FP32C) return SG_EINVAL;
-        if (c->st != ctxs[0]->st || c->prm.G != ctxs[0]->prm.G || c->prm.eps != ctxs[0]->prm.eps)
+        if (c->st != ctxs[0]->st || c->prm.G != ctxs[0]->prm.G || c->prm.eps != ctxs[0]->prm.eps ||
+            c->prm.grav_reorder != ctxs[0]->prm.grav_reorder)
             return SG_EINVAL;
         sg_ens_sys& S = sys[(size_t)k];
         sg_grav_sorted_ptrs(c->at<void>(c->L.gsorted), c->n, &S.xs, &S.ys, &S.zs, &S.ms, &S.sbox);
@@ -1196,19 +1235,25 @@ sg_status sg_ensemble_run(sg_ens* e, double dt, int64_t nsteps, uint32_t flags, 
     if (use_graph && nsteps >= 2 && e->st == nullptr)
         return e->fail(SG_EINVAL, "graph capture needs a stream other than the null stream");
     (void)hipGetLastError();
+    // one period of the (common) Morton-order schedule per captured chunk
+    const int64_t P = reorder_period(e->c[0]);
+    const int64_t chunks = nsteps >= 1 ? (nsteps - 1) / P : 0;
     sg_status r;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        if (use_graph && k == 1) break;
-        if ((r = ens_step(e, dt, flags)) != SG_OK) return r;
-    }
-    if (!use_graph || nsteps < 2)
+    int64_t k = 0;
+    if (!use_graph || chunks < 1) {
+        for (; k < nsteps; ++k)
+            if ((r = ens_step(e, dt, flags)) != SG_OK) return r;
         return hipStreamSynchronize(e->st) == hipSuccess ? SG_OK
                                                           : e->fail(SG_EDEVICE, "stream sync failed");
+    }
+    if ((r = ens_step(e, dt, flags)) != SG_OK) return r;
+    ++k;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     if (hipStreamBeginCapture(e->st, hipStreamCaptureModeRelaxed) != hipSuccess)
         return e->fail(SG_EDEVICE, "hipStreamBeginCapture failed");
-    sg_status rc = ens_step(e, dt, flags);
+    sg_status rc = SG_OK;
+    for (int64_t j = 0; j < P && rc == SG_OK; ++j) rc = ens_step(e, dt, flags);
     hipError_t ec = hipStreamEndCapture(e->st, &graph);
     if (rc != SG_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -1219,8 +1264,9 @@ sg_status sg_ensemble_run(sg_ens* e, double dt, int64_t nsteps, uint32_t flags, 
         (void)hipGraphDestroy(graph);
         return e->fail(SG_EDEVICE, "hipGraphInstantiate failed");
     }
-    for (int64_t k = 1; k < nsteps && rc == SG_OK; ++k)
+    for (int64_t q = 0; q < chunks && rc == SG_OK; ++q, k += P)
         if (hipGraphLaunch(exec, e->st) != hipSuccess) rc = e->fail(SG_EDEVICE, "hipGraphLaunch failed");
+    for (; k < nsteps && rc == SG_OK; ++k) rc = ens_step(e, dt, flags);
     if (hipStreamSynchronize(e->st) != hipSuccess && rc == SG_OK)
         rc = e->fail(SG_EDEVICE, "stream sync failed");
     (void)hipGraphExecDestroy(exec);

@@ -595,7 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_sorted_boxes(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const double* __restrict__ m, const int32_t* __restrict__ order, int64_t n,
     double* __restrict__ xs, double* __restrict__ ys, double* __restrict__ zs,
-    double* __restrict__ ms, box6* __restrict__ sbox) {
+    double* __restrict__ ms, box6* __restrict__ sbox, uint32_t* __restrict__ err) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool v = i < n;
     double p[3] = {0, 0, 0};
@@ -609,6 +609,10 @@ __global__ __launch_bounds__(kBlock) void k_sorted_boxes(
         ys[i] = p[1];
         zs[i] = p[2];
         ms[i] = m[t];
+        // every particle passes here once per preparation, also when the
+        // Morton order (whose key pass checks positions too) is reused
+        if (!(__builtin_isfinite(p[0]) && __builtin_isfinite(p[1]) && __builtin_isfinite(p[2])))
+            atomicOr(err, SGE_GNONFINITE);
     }
     box6 b;
     for (int d = 0; d < 3; ++d) {
@@ -786,14 +790,15 @@ int sg_grav_ensemble_blocks_per_cu(int ipl, int tile, int with_pot) {
 }
 
 int sg_launch_grav_sorted(const sg_grav_args& a_in, hipStream_t st) {
-    if (!a_in.order || !a_in.sorted || !a_in.x || !a_in.y || !a_in.z || !a_in.m || a_in.n < 1)
+    if (!a_in.order || !a_in.sorted || !a_in.x || !a_in.y || !a_in.z || !a_in.m || !a_in.err ||
+        a_in.n < 1)
         return -1;
     sg_grav_args a = a_in;
     sorted_views(a);
     const unsigned nb = (unsigned)((a.n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_sorted_boxes, dim3(nb), dim3(kBlock), 0, st, a.x, a.y, a.z, a.m, a.order,
                        a.n, (double*)a.xs, (double*)a.ys, (double*)a.zs, (double*)a.ms,
-                       (box6*)a.sbox);
+                       (box6*)a.sbox, a.err);
     return 0;
 }
 

@@ -171,10 +171,12 @@ struct sg_grav_args {
     const void* sbox;                   // (set by the launcher) sub-tile boxes
     double *gx, *gy, *gz, *gpot;        // outputs [n], particle order
     double* part;                       // split partials [4][split][n] when split > 1
+    uint32_t* err;                      // device error word (non-finite positions)
 };
 size_t sg_grav_sorted_bytes(int64_t n);
 // FP32C: Morton-ordered copies of x, y, z, m and the boxes of their
-// 64-particle runs (needs a.order and a.sorted).
+// 64-particle runs (needs a.order and a.sorted); a non-finite position
+// sets SGE_GNONFINITE in *a.err.
 // Both return -1 (and launch nothing) when a required pointer is missing.
 int sg_launch_grav_sorted(const sg_grav_args& a, hipStream_t st);
 int sg_launch_gravity(const sg_grav_args& a, hipStream_t st);

@@ -34,6 +34,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--reorder", type=int, default=0,
+                    help="gravity preparations per Morton-order recomputation (0 = every one)")
     args = ap.parse_args()
     import torch
     from paper_1807_08116_amd import ic
@@ -54,6 +56,8 @@ def main():
         big = max(states, key=lambda s: len(s["x"]))
         shape["cell_scale_log2"] = autotune.tune_cells(big, sg.SG_FP32C, reps=2, verbose=True)
         log("autotuned ensemble launch %s (%.1fs)" % (shape, time.perf_counter() - t))
+    if args.reorder:
+        shape["grav_reorder"] = args.reorder
     ens = sg.Ensemble(states, **shape)
     st = ens.stream
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -78,12 +82,17 @@ def main():
     ms_single = timed(one_by_one)
     log("one by one:      %.2f ms (%.3e pairs/s)" % (ms_single, pairs / ms_single * 1e3))
 
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    ens.run(args.dt, args.steps, sg.SG_POT, use_graph=True)
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t
-    log("%d graph-captured ensemble steps: %.3f s/step" % (args.steps, sec / args.steps))
+    # steps, graph-captured (one capture per run, chunks of one Morton-order
+    # period) and eager (the host enqueues every launch of every step)
+    sec = {}
+    for graph in (True, False):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ens.run(args.dt, args.steps, sg.SG_POT, use_graph=graph)
+        torch.cuda.synchronize()
+        sec[graph] = time.perf_counter() - t
+        log("%d %s ensemble steps: %.3f s/step"
+            % (args.steps, "graph-captured" if graph else "eager", sec[graph] / args.steps))
     out = {
         "workload": "%d independent collisions, N log-uniform in [8192, 262144] x %g"
                     % (len(states), args.scale),
@@ -91,7 +100,9 @@ def main():
         "batched_gravity_ms": ms_batched, "batched_pairs_per_s": pairs / ms_batched * 1e3,
         "one_by_one_gravity_ms": ms_single, "one_by_one_pairs_per_s": pairs / ms_single * 1e3,
         "batched_speedup": ms_single / ms_batched,
-        "steps": args.steps, "steps_per_s": args.steps / sec, "graph": True, "precision": "fp32c",
+        "steps": args.steps, "steps_per_s_graph": args.steps / sec[True],
+        "steps_per_s_eager": args.steps / sec[False], "precision": "fp32c",
+        "grav_reorder": args.reorder or 1,
         "launch": shape or "automatic",
     }
     print(json.dumps(out), flush=True)

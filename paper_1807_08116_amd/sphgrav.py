@@ -51,7 +51,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("grav_ipl", C.c_int32), ("grav_split", C.c_int32),
                 ("grav_variant", C.c_int32), ("grav_tile", C.c_int32),
                 ("cell_scale_log2", C.c_int32), ("step_serial", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("grav_reorder", C.c_int32)]
 
 
 class Caps(C.Structure):
@@ -153,9 +153,9 @@ def lib():
 
 def make_params(G=1.0, eps=0.01, gamma=5.0 / 3.0, alpha=1.0, beta=2.0, eta=0.1,
                 precision=SG_FP64, grav_ipl=0, grav_split=0, grav_variant=0, grav_tile=0,
-                cell_scale_log2=0, step_serial=0):
+                cell_scale_log2=0, step_serial=0, grav_reorder=0):
     return Params(G, eps, gamma, alpha, beta, eta, precision, grav_ipl, grav_split, grav_variant,
-                  grav_tile, cell_scale_log2, step_serial)
+                  grav_tile, cell_scale_log2, step_serial, grav_reorder)
 
 
 def default_caps(n_gas, n_halo, cell_cap=None, nnz_cap=None):

@@ -60,16 +60,18 @@ def test_workspace_validation(sg):
                 dict(grav_variant=1, eps=1e-20),
                 dict(precision=1, grav_variant=2), dict(precision=1, eps=1e-20),
                 dict(grav_tile=64), dict(grav_tile=1024), dict(cell_scale_log2=2),
-                dict(cell_scale_log2=-2), dict(step_serial=2), dict(step_serial=-1)):
+                dict(cell_scale_log2=-2), dict(step_serial=2), dict(step_serial=-1),
+                dict(grav_reorder=-1), dict(grav_reorder=1025)):
         assert sg.workspace_bytes(sg.make_params(**bad), caps) == 0, bad
     for ok in (dict(grav_tile=128), dict(grav_tile=512), dict(cell_scale_log2=-1),
                dict(cell_scale_log2=1), dict(grav_variant=2, eps=1e-20),
                dict(grav_variant=3), dict(grav_variant=4, eps=1e-20), dict(eps=1e-20),
-               dict(step_serial=1)):
+               dict(step_serial=1), dict(grav_reorder=1), dict(grav_reorder=1024)):
         assert sg.workspace_bytes(sg.make_params(**ok), caps) > 0, ok
-    p = sg.make_params()
-    p.reserved[0] = 1
-    assert sg.workspace_bytes(p, caps) == 0
+    # the diagnostics slot of a captured chunk grows from 80 bytes (one
+    # 256-byte-aligned slot) to 10 doubles per step of the reorder period
+    assert sg.workspace_bytes(sg.make_params(grav_reorder=64), caps) == \
+        sg.workspace_bytes(good, caps) + 64 * 80 - 256
     assert sg.workspace_bytes(good, sg.Caps(0, 0, 0, 0)) == 0
     assert sg.workspace_bytes(good, sg.Caps(-1, 5, 5, 5)) == 0
     assert sg.workspace_bytes(good, sg.Caps(10, 0, 0, 10)) == 0      # gas without cells

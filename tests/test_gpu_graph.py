@@ -136,3 +136,56 @@ def test_ensemble_overlapped_steps_equal_serial(sg):
     for a, b in zip(*out):
         for f in FIELDS:
             np.testing.assert_array_equal(a[f], b[f], err_msg=f)
+
+
+# ------------------------------------------------ Morton-order period --
+
+def test_reorder_period_graph_equals_eager_and_stays_accurate(sg, orc, c0):
+    # grav_reorder = 4: the Morton order is recomputed every 4th gravity
+    # preparation.  A captured chunk holds 4 steps, so 1 eager + 2 chunks +
+    # 2 tail steps (9 steps) must equal 9 eager steps bit for bit, and the
+    # gravity of one more step (in the order recomputed two steps earlier)
+    # stays within the FP32C bound of the oracle's.
+    dt = 2e-3
+    eager = sg.Engine(c0, precision=sg.SG_FP32C, grav_reorder=4, stream="new")
+    h_e = eager.ctx.run(dt, 9, sg.SG_POT, use_graph=False).cpu().numpy()
+    graph = sg.Engine(c0, precision=sg.SG_FP32C, grav_reorder=4, stream="new")
+    h_g = graph.ctx.run(dt, 9, sg.SG_POT, use_graph=True).cpu().numpy()
+    np.testing.assert_array_equal(h_g, h_e)
+    for f in FIELDS:
+        np.testing.assert_array_equal(graph.numpy(f), eager.numpy(f), err_msg=f)
+    # the step after the run reuses a stale order; gravity part vs oracle
+    eager.ctx.step(dt, sg.SG_POT)
+    eager.ctx.sync()
+    x, y, z, m = (eager.numpy(f) for f in ("x", "y", "z", "m"))
+    gx, gy, gz, _ = orc.gravity(x, y, z, m, 1.0, 0.01)
+    ref = np.stack([gx, gy, gz], 1)
+    got = eager.ctx.export(sg.SG_X_ACC_GRAV).T
+    assert np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2)) < 1e-6
+    # a period of 1 (the default) recomputes every time: a different
+    # trajectory only at rounding level
+    fresh = sg.Engine(c0, precision=sg.SG_FP32C, stream="new")
+    fresh.ctx.run(dt, 9, sg.SG_POT, use_graph=False)
+    for f in ("x", "vx"):
+        a, b = graph.numpy(f), fresh.numpy(f)           # 9 steps each
+        assert np.max(np.abs(a - b)) < 1e-5 * np.max(np.abs(b)), f
+
+
+def test_reorder_period_ensemble_equals_single(sg):
+    # ensembles follow each system's period: eager, captured (chunks of
+    # 3 steps) and single-context runs agree bit for bit
+    from paper_1807_08116_amd import ic
+    states = ic.ensemble(nsys=4, scale=0.03)
+    dt = 1e-3
+    eager = sg.Ensemble(states, grav_reorder=3)
+    eager.run(dt, 8, sg.SG_POT, use_graph=False)
+    graph = sg.Ensemble(states, grav_reorder=3)
+    graph.run(dt, 8, sg.SG_POT, use_graph=True)
+    for st, e1, e2 in zip(states, eager.engines, graph.engines):
+        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_ipl=2, grav_tile=512,
+                           grav_reorder=3)
+        single.ctx.run(dt, 8, sg.SG_POT, use_graph=False)
+        for f in FIELDS:
+            a, b, c = e1.numpy(f), e2.numpy(f), single.numpy(f)
+            np.testing.assert_array_equal(a, b, err_msg="graph " + f)
+            np.testing.assert_array_equal(a, c, err_msg="single " + f)
