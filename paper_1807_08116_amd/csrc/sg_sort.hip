@@ -214,8 +214,15 @@ __global__ __launch_bounds__(kBlock) void k_grid_hmin(const double* __restrict__
             mn = o < mn ? o : mn;
         }
     }
+    // wavefront, then workgroup minimum: one global atomic per workgroup
+    __shared__ unsigned long long s_mn[kBlock / 64];
     mn = wave_min_u64(mn);
-    if (lane_id() == 0 && mn != ~0ull) atomicMin(&g->hmin_bits, mn);
+    if (lane_id() == 0) s_mn[threadIdx.x >> 6] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / 64; ++k) mn = s_mn[k] < mn ? s_mn[k] : mn;
+        if (mn != ~0ull) atomicMin(&g->hmin_bits, mn);
+    }
     if (bad) atomicOr(&g->err, SGE_NONFINITE);
 }
 
@@ -482,12 +489,27 @@ __global__ __launch_bounds__(kBlock) void k_gbox(const double* __restrict__ x,
             mx[d] = o > mx[d] ? o : mx[d];
         }
     }
+    // wavefront, then workgroup, then one global atomic per bound and
+    // workgroup (same-address atomics from every wavefront serialise in L2)
+    __shared__ unsigned long long s_lo[3][kBlock / 64], s_hi[3][kBlock / 64];
+    const int w = threadIdx.x >> 6;
     for (int d = 0; d < 3; ++d) {
         unsigned long long a = wave_min_u64(mn[d]), b = wave_max_u64(mx[d]);
         if (lane_id() == 0) {
-            atomicMin(&g->glo[d], a);
-            atomicMax(&g->ghi[d], b);
+            s_lo[d][w] = a;
+            s_hi[d][w] = b;
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int d = threadIdx.x;
+        unsigned long long a = s_lo[d][0], b = s_hi[d][0];
+        for (int k = 1; k < kBlock / 64; ++k) {
+            a = s_lo[d][k] < a ? s_lo[d][k] : a;
+            b = s_hi[d][k] > b ? s_hi[d][k] : b;
+        }
+        atomicMin(&g->glo[d], a);
+        atomicMax(&g->ghi[d], b);
     }
     if (bad) atomicOr(&g->err, SGE_GNONFINITE);
 }
@@ -708,7 +730,7 @@ void sg_launch_morton_order(const double* x, const double* y, const double* z, i
     const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
     unsigned nb = grid_for(n, kBlock);
     hipLaunchKernelGGL(k_gbox_reset, dim3(1), dim3(64), 0, st, g);
-    hipLaunchKernelGGL(k_gbox, dim3(nb > 1024 ? 1024 : nb), dim3(kBlock), 0, st, x, y, z, n, g);
+    hipLaunchKernelGGL(k_gbox, dim3(nb > 512 ? 512 : nb), dim3(kBlock), 0, st, x, y, z, n, g);
     hipLaunchKernelGGL(k_morton_keys, dim3(nb), dim3(kBlock), 0, st, x, y, z, n, g, k[0], v[0]);
     int cur = 0;
     for (int pass = 0; pass < 4; ++pass) {
