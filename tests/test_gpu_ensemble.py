@@ -31,6 +31,35 @@ def states():
     return ic.ensemble(nsys=5, scale=0.05)          # 5 systems of ~400..13000 particles
 
 
+@pytest.mark.parametrize("other", [dict(eps=0.02), dict(grav_reorder=4), dict(precision="fp64"),
+                                   dict(stream="new")])
+def test_ensemble_create_rejects_mismatched_contexts(sg, states, other):
+    # every context of an ensemble must be FP32C and share G, eps, the
+    # Morton-order period and the stream; anything else is SG_EINVAL
+    import ctypes as C
+    import torch
+    stream = torch.cuda.Stream()
+    kw = dict(other)
+    prec = sg.SG_FP64 if kw.pop("precision", None) == "fp64" else sg.SG_FP32C
+    st2 = "new" if kw.pop("stream", None) else stream
+    a = sg.Engine(states[0], precision=sg.SG_FP32C, stream=stream)
+    b = sg.Engine(states[1], precision=prec, stream=st2, **kw)
+    L = sg.lib()
+    nbytes = L.sg_ensemble_bytes(2, a.n + b.n)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) & ~255
+    handles = (C.c_void_p * 2)(a.ctx.h.value, b.ctx.h.value)
+    h = C.c_void_p()
+    torch.cuda.synchronize()
+    rc = L.sg_ensemble_create(handles, 2, C.c_void_p(ptr), nbytes, C.byref(h))
+    assert rc == sg.SG_EINVAL and not h.value
+    # the same two systems with matching contexts are accepted
+    b_ok = sg.Engine(states[1], precision=sg.SG_FP32C, stream=stream)
+    handles = (C.c_void_p * 2)(a.ctx.h.value, b_ok.ctx.h.value)
+    assert L.sg_ensemble_create(handles, 2, C.c_void_p(ptr), nbytes, C.byref(h)) == sg.SG_OK
+    L.sg_ensemble_destroy(h)
+
+
 @pytest.mark.parametrize("ipl,tile", [(2, 256), (1, 128), (4, 512)])
 def test_ensemble_gravity_matches_single(sg, orc, states, ipl, tile):
     ens = sg.Ensemble(states, grav_ipl=ipl, grav_tile=tile)
