@@ -141,6 +141,34 @@ def test_c0_forces(sg, orc, c0, c0_ref, precision):
     assert e_pot < tol
 
 
+def _interleave10(v):
+    # bit b of v goes to bit 3b (the Morton spreading of a 10-bit coordinate)
+    out = np.zeros_like(v)
+    for b in range(10):
+        out |= ((v >> b) & 1) << (3 * b)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_gravity_order_is_the_stable_morton_sort(sg, c0, precision):
+    # The gravity kernels visit particles in the order of 30-bit Morton
+    # keys: each coordinate quantised to 10 bits over the cube of side
+    # (largest extent) x (1 + 2^-20) anchored at the per-axis minimum, keys
+    # interleaved x, y, z from bit 0, ties in particle order.  The exported
+    # order equals that stable sort, bit for bit.
+    p = sg.SG_FP64 if precision == "fp64" else sg.SG_FP32C
+    eng = sg.Engine(c0, precision=p)
+    eng.ctx.compute_accel(sg.SG_GRAV)
+    got = eng.ctx.export(sg.SG_X_GORDER)
+    P = np.stack([np.asarray(c0[f], dtype=np.float64) for f in ("x", "y", "z")])
+    lo = P.min(axis=1)
+    ext = np.max(P.max(axis=1) - lo)
+    scale = 1024.0 / (ext * (1.0 + 2.0 ** -20))
+    q = np.clip((P - lo[:, None]) * scale, 0.0, 1023.0).astype(np.uint64)
+    key = _interleave10(q[0]) | (_interleave10(q[1]) << 1) | (_interleave10(q[2]) << 2)
+    np.testing.assert_array_equal(got, np.argsort(key, kind="stable"))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_c0_force_parts(sg, orc, c0, c0_ref, precision):
     # the SPH and gravity parts separately (the FP32C form's error is
