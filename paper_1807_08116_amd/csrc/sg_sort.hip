@@ -549,34 +549,43 @@ __global__ __launch_bounds__(kBlock) void k_morton_keys(const double* __restrict
     vals[i] = (int32_t)i;
 }
 
+// Morton keys have 30 bits: three passes of 10-bit digits.
+constexpr int kRadixBits = 10;
+constexpr int kBuckets = 1 << kRadixBits;
+constexpr int kRadixPasses = 3;
+
 // Digit histogram of one tile, stored digit-major: hist[d * ntiles + tile].
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                        int64_t n, int shift, int64_t ntiles,
                                                        int32_t* __restrict__ hist) {
-    __shared__ int32_t s_h[256];
-    s_h[threadIdx.x] = 0;
+    __shared__ int32_t s_h[kBuckets];
+    for (int t = threadIdx.x; t < kBuckets; t += kBlock) s_h[t] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     for (int k = 0; k < kRadixItems; ++k) {
         int64_t i = base + k * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 255u], 1);
+        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & (kBuckets - 1)], 1);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
+    for (int t = threadIdx.x; t < kBuckets; t += kBlock)
+        hist[(int64_t)t * ntiles + blockIdx.x] = s_h[t];
 }
 
 // Stable scatter: element order inside the tile is preserved within each
-// digit (chunk by chunk, wave by wave, lane by lane).
+// digit (chunk by chunk, wave by wave, lane by lane).  Per chunk, the first
+// lane of each (wave, digit) group publishes the group's size; after the
+// writes it adds that size to the digit's running count and clears its slot.
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
     int64_t ntiles, const int64_t* __restrict__ offs, uint32_t* __restrict__ kout,
     int32_t* __restrict__ vout) {
-    __shared__ int32_t s_run[256];
-    __shared__ int32_t s_w[kBlock / 64][256];
+    __shared__ int32_t s_run[kBuckets];
+    __shared__ int32_t s_w[kBlock / 64][kBuckets];
     const int wave = threadIdx.x >> 6;
-    const unsigned lane = lane_id();
-    s_run[threadIdx.x] = 0;
-    for (int w = 0; w < kBlock / 64; ++w) s_w[w][threadIdx.x] = 0;
+    for (int t = threadIdx.x; t < kBuckets; t += kBlock) {
+        s_run[t] = 0;
+        for (int w = 0; w < kBlock / 64; ++w) s_w[w][t] = 0;
+    }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     for (int k = 0; k < kRadixItems; ++k) {
@@ -584,14 +593,16 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         const bool valid = i < n;
         const uint32_t key = valid ? kin[i] : 0u;
         const int32_t val = valid ? vin[i] : 0;
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t d = (key >> shift) & (kBuckets - 1);
         unsigned long long peers = __ballot(valid);
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < kRadixBits; ++b) {
             unsigned long long bb = __ballot(valid && ((d >> b) & 1u));
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
         const unsigned r = rank_below(peers);
-        if (valid && r == 0) s_w[wave][d] = __builtin_popcountll(peers);
+        const int cnt = __builtin_popcountll(peers);
+        const bool lead = valid && r == 0;
+        if (lead) s_w[wave][d] = cnt;
         __syncthreads();
         if (valid) {
             int32_t pre = 0;
@@ -601,15 +612,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
             vout[dest] = val;
         }
         __syncthreads();
-        int32_t add = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            add += s_w[w][threadIdx.x];
-            s_w[w][threadIdx.x] = 0;
+        if (lead) {
+            atomicAdd(&s_run[d], cnt);
+            s_w[wave][d] = 0;
         }
-        s_run[threadIdx.x] += add;
         __syncthreads();
     }
-    (void)lane;
 }
 
 inline unsigned grid_for(int64_t n, int per_block) {
@@ -693,7 +701,7 @@ static void morton_layout(int64_t n, size_t* o_k1, size_t* o_v0, size_t* o_v1, s
                           size_t* o_offs, size_t* o_scan, size_t* total) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
-    const int64_t nh = 256 * (ntiles > 0 ? ntiles : 1);
+    const int64_t nh = kBuckets * (ntiles > 0 ? ntiles : 1);
     size_t o = 0;
     o += al(sizeof(uint32_t) * (size_t)n);  // k0 at 0
     *o_k1 = o;
@@ -733,12 +741,12 @@ void sg_launch_morton_order(const double* x, const double* y, const double* z, i
     hipLaunchKernelGGL(k_gbox, dim3(nb > 512 ? 512 : nb), dim3(kBlock), 0, st, x, y, z, n, g);
     hipLaunchKernelGGL(k_morton_keys, dim3(nb), dim3(kBlock), 0, st, x, y, z, n, g, k[0], v[0]);
     int cur = 0;
-    for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 8 * pass;
+    for (int pass = 0; pass < kRadixPasses; ++pass) {
+        const int shift = kRadixBits * pass;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kBlock), 0, st, k[cur], n,
                            shift, ntiles, hist);
-        sg_launch_scan(hist, offs, 256 * ntiles, nullptr, 256 * ntiles, scan_tmp, st);
-        int32_t* vo = (pass == 3) ? order : v[cur ^ 1];
+        sg_launch_scan(hist, offs, kBuckets * ntiles, nullptr, kBuckets * ntiles, scan_tmp, st);
+        int32_t* vo = (pass == kRadixPasses - 1) ? order : v[cur ^ 1];
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kBlock), 0, st, k[cur],
                            v[cur], n, shift, ntiles, offs, k[cur ^ 1], vo);
         cur ^= 1;
