@@ -140,16 +140,20 @@ def test_ensemble_overlapped_steps_equal_serial(sg):
 
 # ------------------------------------------------ Morton-order period --
 
-def test_reorder_period_graph_equals_eager_and_stays_accurate(sg, orc, c0):
+@pytest.mark.parametrize("form", ["fp32c", "fp64"])
+def test_reorder_period_graph_equals_eager_and_stays_accurate(sg, orc, c0, form):
     # grav_reorder = 4: the Morton order is recomputed every 4th gravity
-    # preparation.  A captured chunk holds 4 steps, so 1 eager + 2 chunks +
-    # 2 tail steps (9 steps) must equal 9 eager steps bit for bit, and the
-    # gravity of one more step (in the order recomputed two steps earlier)
-    # stays within the FP32C bound of the oracle's.
+    # preparation (FP32C and the FP64 expanded kernel).  A captured chunk
+    # holds 4 steps, so 1 eager + 2 chunks + 2 tail steps (9 steps) must
+    # equal 9 eager steps bit for bit, and the gravity of one more step (in
+    # the order recomputed two steps earlier) stays within the form's bound
+    # of the oracle's.
+    p = sg.SG_FP32C if form == "fp32c" else sg.SG_FP64
+    tol = 1e-6 if form == "fp32c" else 1e-12
     dt = 2e-3
-    eager = sg.Engine(c0, precision=sg.SG_FP32C, grav_reorder=4, stream="new")
+    eager = sg.Engine(c0, precision=p, grav_reorder=4, stream="new")
     h_e = eager.ctx.run(dt, 9, sg.SG_POT, use_graph=False).cpu().numpy()
-    graph = sg.Engine(c0, precision=sg.SG_FP32C, grav_reorder=4, stream="new")
+    graph = sg.Engine(c0, precision=p, grav_reorder=4, stream="new")
     h_g = graph.ctx.run(dt, 9, sg.SG_POT, use_graph=True).cpu().numpy()
     np.testing.assert_array_equal(h_g, h_e)
     for f in FIELDS:
@@ -161,10 +165,10 @@ def test_reorder_period_graph_equals_eager_and_stays_accurate(sg, orc, c0):
     gx, gy, gz, _ = orc.gravity(x, y, z, m, 1.0, 0.01)
     ref = np.stack([gx, gy, gz], 1)
     got = eager.ctx.export(sg.SG_X_ACC_GRAV).T
-    assert np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2)) < 1e-6
+    assert np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2)) < tol
     # a period of 1 (the default) recomputes every time: a different
     # trajectory only at rounding level
-    fresh = sg.Engine(c0, precision=sg.SG_FP32C, stream="new")
+    fresh = sg.Engine(c0, precision=p, stream="new")
     fresh.ctx.run(dt, 9, sg.SG_POT, use_graph=False)
     for f in ("x", "vx"):
         a, b = graph.numpy(f), fresh.numpy(f)           # 9 steps each
