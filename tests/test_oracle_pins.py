@@ -504,3 +504,123 @@ def test_kernel_values_golden(orc, h):
         assert abs(orc.W(xi * h, h) * scale - w) < 1e-14
         assert abs(orc.Wp(xi * h, h) * scale - wp) < 1e-14
         assert abs(orc.dWp_dxi(xi * h, h) * scale - dwp) < 1e-14
+
+
+# ------------------------------ unequal smoothing lengths, masses, energies --
+# Hand-derived closed forms for a pair with h_1 != h_2, m_1 != m_2 and
+# e_1 != e_2 (derivation in tests/golden/two_particle_unequal.md, Sec. 2.2):
+# they fix h_ij = (h_i + h_j)/2 in the density and in grad W_p, the means
+# rho_ij and c_ij of the viscosity, and which mass enters each sum.
+
+def _unequal_pair(v1):
+    x = np.array([-0.75, 0.75]); y = np.zeros(2); z = np.zeros(2)
+    m = np.array([1.0, 2.0]); h = np.array([1.0, 3.0]); e = np.array([1.0, 2.0])
+    vx = np.array([v1, -v1])
+    off = np.array([0, 1, 2], dtype=np.int64); idx = np.array([1, 0], dtype=np.int32)
+    return x, y, z, vx, m, h, e, off, idx
+
+
+UNEQ_RHO = np.array([1145.0 / (1024.0 * PI), 7363.0 / (55296.0 * PI)])
+UNEQ_P = 2048.0 * PI / 3435.0 + 73728.0 * PI / 7363.0       # P_1 + P_2
+UNEQ_G = 1125.0 / (16384.0 * PI)                             # |grad W_p|
+
+
+def test_two_particle_unequal_density(orc):
+    x, y, z, vx, m, h, e, off, idx = _unequal_pair(0.0)
+    assert orc.pred((x[0], 0, 0), h[0], (x[1], 0, 0), h[1])     # |r| < h_1 + h_2
+    rho = orc.density(x, y, z, m, h, off, idx)
+    np.testing.assert_allclose(rho, UNEQ_RHO, rtol=1e-15)
+    p, c = orc.eos(rho, e, 5 / 3)
+    np.testing.assert_allclose(p / rho ** 2, [2048 * PI / 3435, 73728 * PI / 7363], rtol=1e-14)
+    np.testing.assert_allclose(c, [math.sqrt(10) / 3, math.sqrt(20) / 3], rtol=1e-15)
+
+
+@pytest.mark.parametrize("approaching", [False, True])
+def test_two_particle_unequal_forces(orc, approaching):
+    x, y, z, vx, m, h, e, off, idx = _unequal_pair(0.25 if approaching else -0.25)
+    zero = np.zeros(2)
+    ax, ay, az, de = orc.sph_force(x, y, z, vx, zero, zero, m, h, UNEQ_RHO, e,
+                                   5 / 3, 1.0, 2.0, 0.1, off, idx)
+    Pi = UNEQ_P
+    if approaching:
+        mu = -30.0 / 53.0
+        c12 = (math.sqrt(10) + math.sqrt(20)) / 6
+        rho12 = 0.5 * (UNEQ_RHO[0] + UNEQ_RHO[1])
+        Pi += mu * (2.0 * mu - 1.0 * c12) / rho12
+    g = UNEQ_G
+    np.testing.assert_allclose(ax, [-2 * Pi * g, Pi * g], rtol=1e-14)
+    sgn = 1.0 if approaching else -1.0
+    np.testing.assert_allclose(de, [sgn * Pi * g / 2, sgn * Pi * g / 4], rtol=1e-14)
+    assert np.all(ay == 0) and np.all(az == 0)
+    # the energy identity holds for the unequal pair as well
+    assert abs(np.sum(m * (vx * ax + de))) < 1e-14 * np.sum(m * np.abs(de))
+
+
+def test_cfl_unequal_pair_closed_form(orc):
+    # Eq. (dt-stability) with every term non-zero (derivation in
+    # tests/golden/two_particle_unequal.md): s = 1/2, c_max = 0.4,
+    # |mu|_max = 10/7, and particle 2's sqrt(s (|Q| + |E|)) = 2 binds.
+    x = np.array([-0.25, 0.25]); y = np.zeros(2); z = np.zeros(2)
+    vx = np.array([0.5, -0.5]); zero = np.zeros(2)
+    h = np.ones(2); c = np.array([0.3, 0.5])
+    qx = np.array([3.0, 0.0]); qy = np.array([4.0, 0.0]); E = np.array([1.0, -8.0])
+    off = np.array([0, 1, 2], dtype=np.int64); idx = np.array([1, 0], dtype=np.int32)
+    dt = orc.cfl_dt(x, y, z, vx, zero, zero, h, c, qx, qy, zero, E, 0.6, 1.0, 2.0, 0.1,
+                    off, idx)
+    expect = 0.3 / (0.88 + 24.0 / 7.0 + 2.0)
+    assert abs(dt / expect - 1) < 1e-15, (dt, expect)
+    # with particle 2 at rest in Q and E, particle 1's root term sqrt(1/2 * 6)
+    # binds: |Q_1| is the vector norm 5 (not |3| + |4|)
+    dt1 = orc.cfl_dt(x, y, z, vx, zero, zero, h, c, qx, qy, zero, np.array([1.0, 0.0]),
+                     0.6, 1.0, 2.0, 0.1, off, idx)
+    expect1 = 0.3 / (0.88 + 24.0 / 7.0 + math.sqrt(3.0))
+    assert abs(dt1 / expect1 - 1) < 1e-15, (dt1, expect1)
+
+
+def _pair_state(v1):
+    x, y, z, vx, m, h, e, off, idx = _unequal_pair(v1)
+    return {"ng": 2, "x": x, "y": y, "z": z, "vx": vx, "vy": np.zeros(2), "vz": np.zeros(2),
+            "m": m, "h": h, "e": e}
+
+
+@pytest.mark.parametrize("approaching,t_end", [(False, 0.4), (True, 0.1)])
+def test_gas_predictor_corrector_second_order(orc, approaching, t_end):
+    # Eqs. (v-predictor)..(e-corrector) on a gas-only system (G = 0: the
+    # pair above, receding, or approaching with the viscosity switched on
+    # for the whole interval).  The scheme is second order, so its error at
+    # t_end against a tight DOP853 solution of the same equations of motion
+    # (dr/dt = v, dv/dt = Q, de/dt = E, with Q and E the oracle's sums at
+    # the current state, density refreshed at the current positions) falls
+    # ~4x per halving of dt, in the positions, velocities and energies.
+    from scipy.integrate import solve_ivp
+    prm = dict(G=0.0, eps=0.01, gamma=5 / 3, alpha=1.0, beta=2.0, eta=0.1)
+    st0 = _pair_state(0.25 if approaching else -0.25)
+
+    def rhs(t, yv):
+        st = dict(st0)
+        st["x"], st["vx"], st["e"] = yv[0:2].copy(), yv[2:4].copy(), yv[4:6].copy()
+        f = orc.forces(st, prm)
+        ax, _, _ = orc.total_accel(st, f)
+        return np.concatenate([yv[2:4], ax, f["dedt"]])
+
+    y0 = np.concatenate([st0["x"], st0["vx"], st0["e"]])
+    sol = solve_ivp(rhs, (0.0, t_end), y0, method="DOP853", rtol=1e-13, atol=1e-15)
+    ref = sol.y[:, -1]
+    if approaching:
+        assert np.all(sol.y[2, :] - sol.y[3, :] > 0)          # r.v < 0 throughout
+
+    def run(dt):
+        st, cache = st0, None
+        for _ in range(int(round(t_end / dt))):
+            st, cache = orc.pc_step(st, prm, dt, cache)
+        return np.concatenate([st["x"], st["vx"], st["e"]])
+
+    errs = []
+    for dt in (t_end / 20, t_end / 40, t_end / 80):
+        d = run(dt) - ref
+        errs.append([np.max(np.abs(d[0:2])), np.max(np.abs(d[2:4])), np.max(np.abs(d[4:6]))])
+    errs = np.array(errs)
+    for k, name in enumerate(("x", "v", "e")):
+        for a, b in ((0, 1), (1, 2)):
+            ratio = errs[a, k] / errs[b, k]
+            assert 3.3 < ratio < 4.7, (name, errs[:, k])
