@@ -14,19 +14,24 @@
  *   allocates or frees device memory: its scratch lives in one caller-owned
  *   workspace blob sized by sg_workspace_bytes().  Host-side it allocates
  *   only the small opaque context.
- * - Streams: all work is enqueued on the HIP stream given to sg_create();
- *   entry points return as soon as the work is enqueued.  Only
- *   sg_sync() and sg_export() wait for the stream.  Inside a step the
- *   gravity runs on a second stream of the context's own (default
- *   priority), forked from the given stream and joined back into it before
- *   the step's last kernels, so every step stays ordered on the given
- *   stream (and can be captured from it).
+ * - Streams: the caller owns them.  All work is enqueued on the HIP
+ *   stream given to sg_create(); entry points return as soon as the work
+ *   is enqueued.  Only sg_status_sync(), sg_export(), sg_profile_read(),
+ *   sg_run(), sg_ensemble_create(), sg_ensemble_run() and the destroy calls
+ *   wait for streams.  Inside a step the gravity runs on the caller's
+ *   second (auxiliary) stream when one was given, forked from the main
+ *   stream and joined back into it before the step's last kernels, so
+ *   every step stays ordered on the main stream (and can be captured from
+ *   it).  The library creates only the events of those forks and joins,
+ *   and, for an ensemble given no gravity stream, one CU-masked stream
+ *   (sg_ensemble_create).
  * - Errors: every call returns an sg_status; nothing aborts and no C++
  *   exception crosses the ABI.  Argument errors are detected on the host
  *   before any HIP call.  Conditions only the device can see (capacity
  *   overflow, bad smoothing lengths, non-finite positions) are latched in
  *   a device error word: the affected kernels then do nothing, and the
- *   next sg_sync() reports the condition and the capacity required.
+ *   next sg_status_sync() reports the condition and the capacity
+ *   required.
  * - Threading: one context per stream; a context is not thread-safe.
  * - Indices are int32 (N < 2^31); CSR offsets are int64.
  */
@@ -71,7 +76,9 @@ typedef enum {
 /* Physical and tuning parameters.
  * G, eps: gravitational constant and Plummer softening length; the
  *   paper's softened pair force (Eq. self-gravity, whose printed
- *   denominator is read as (|r_ij|^2 + eps^2)^{3/2}); eps must be > 0.
+ *   denominator is read as (|r_ij|^2 + eps^2)^{3/2}); eps must be > 0, and
+ *   >= 1e-12 in the SG_FP32C form (so that (r^2 + eps^2)^{-3/2} is finite
+ *   in FP32).
  * gamma: adiabatic index of the ideal-gas law (Eq. e_p_rho), > 1.
  * alpha, beta, eta: artificial-viscosity constants (Sec. 2.2), >= 0, eta > 0.
  * precision: an sg_precision value.
@@ -95,7 +102,7 @@ typedef enum {
  *   side L0 * 2^(l + cell_scale_log2).  It changes cell keys, counts,
  *   offsets and the slot order (so the exported grid arrays and the order
  *   of SPH sums), never which particles are neighbours.
- * step_serial: 0 = in a step, gravity runs on the context's second stream
+ * step_serial: 0 = in a step, gravity runs on the context's auxiliary stream
  *   beside the neighbours -> density -> SPH(corrector) chain (default);
  *   1 = the two one after the other on the context's stream (for kernel
  *   traces whose per-kernel durations should not include waiting beside
@@ -150,10 +157,15 @@ size_t sg_workspace_bytes(const sg_params *prm, const sg_caps *caps);
 
 /* Create a context over a caller-owned workspace of ws_bytes bytes
  * (>= sg_workspace_bytes, 256-byte aligned) on HIP stream `stream`
- * (a hipStream_t; NULL = the default stream).  The workspace must stay
- * allocated until sg_destroy().  Enqueues a clear of the device status. */
+ * (a hipStream_t; NULL = the default stream).  aux_stream: a second
+ * caller-owned stream (hipStream_t) on which each step runs the gravity
+ * beside the neighbour/SPH chain; NULL or equal to `stream`: the two run
+ * one after the other on `stream` (as with step_serial).  Both streams and
+ * the workspace must outlive the context (sg_destroy waits for both
+ * streams).  Enqueues a clear of the device status.  On failure *out is
+ * NULL and sg_last_error(NULL) says why. */
 sg_status sg_create(const sg_params *prm, const sg_caps *caps, void *d_workspace,
-                    size_t ws_bytes, void *stream, sg_ctx **out);
+                    size_t ws_bytes, void *stream, void *aux_stream, sg_ctx **out);
 
 /* Bind a particle state (the "upload" step: the state already sits in
  * device memory owned by the caller).  n_gas <= n_gas_cap, n_halo <=
@@ -177,7 +189,7 @@ sg_status sg_bind_state(sg_ctx *ctx, int64_t n_gas, int64_t n_halo, const sg_sta
  * from origin floor(min/L_l) L_l; keys run level by level, then z, y, x
  * (x fastest).  Device-side conditions (cells or neighbour pairs beyond
  * the capacities, non-finite positions, h <= 0, more than SG_MAX_LEVELS
- * levels) are latched and reported by the next sg_sync. */
+ * levels) are latched and reported by the next sg_status_sync. */
 sg_status sg_build_neighbors(sg_ctx *ctx);
 
 /* SPH density of every gas particle (Eq. SPH-mass-density, self term
@@ -202,7 +214,7 @@ sg_status sg_kick_drift(sg_ctx *ctx, double dt, int32_t phase);
  * gravity] -> SPH(predictor) -> SG_PREDICT -> neighbours -> density ->
  * gravity (once per step, reused by the next predictor) -> SPH(corrector)
  * -> SG_CORRECT.  After SG_PREDICT the gravity runs on the context's
- * second stream beside the neighbours -> density -> SPH(corrector) chain
+ * auxiliary stream beside the neighbours -> density -> SPH(corrector) chain
  * (the two are independent); results equal the sequential order bit for
  * bit.  flags may add SG_POT. */
 sg_status sg_step(sg_ctx *ctx, double dt, uint32_t flags);
@@ -281,10 +293,12 @@ typedef struct {
 sg_status sg_export(sg_ctx *ctx, int32_t what, void *d_dst, int64_t cap_bytes,
                     int64_t *n_out);
 
-/* Wait for the stream, then report the device error word.  On
- * SG_ECAPACITY, need[0] = cells required, need[1] = neighbour pairs
- * required (need may be NULL). */
-sg_status sg_sync(sg_ctx *ctx, int64_t need[2]);
+/* Wait for the stream, then report the device error word (and clear it).
+ * On SG_ECAPACITY, need[0] = cells required, need[1] = neighbour pairs
+ * required (need may be NULL).  SG_ENONFINITE and SG_ERANGE name the other
+ * latched conditions; after any of them the cached lists and forces are
+ * invalid and the next step rebuilds them. */
+sg_status sg_status_sync(sg_ctx *ctx, int64_t need[2]);
 
 /* Ensembles of independent systems (one bound context each, all SG_FP32C,
  * the same G, eps, grav_reorder and stream; SG_EINVAL otherwise).
@@ -296,24 +310,33 @@ sg_status sg_sync(sg_ctx *ctx, int64_t need[2]);
  * The ensemble keeps pointers into the contexts: do not rebind or destroy
  * them while it exists.  d_ws: caller-owned device memory of
  * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task
- * table is uploaded once, synchronously, by sg_ensemble_create. */
+ * table is uploaded once, synchronously, by sg_ensemble_create.
+ * side_streams[0..nside): caller-owned streams (none equal to the
+ * contexts' stream; nside <= 64, at most nsys used) on which the systems'
+ * own launches run side by side; nside = 0 runs everything on the shared
+ * stream.  grav_stream: the caller's stream for the batched gravity beside
+ * those launches, or NULL: then, if side streams are given, the ensemble
+ * creates (and destroys) one stream with every CU in its mask, because a
+ * stream of that kind gets a hardware queue of its own, where an ordinary
+ * stream may share a queue with a side stream and hold that side stream's
+ * launches behind the long gravity kernel.  Every stream must outlive the
+ * ensemble. */
 typedef struct sg_ens sg_ens;   /* opaque */
 size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles);
 sg_status sg_ensemble_create(sg_ctx *const *ctxs, int32_t nsys, void *d_ws, size_t ws_bytes,
+                             void *const *side_streams, int32_t nside, void *grav_stream,
                              sg_ens **out);
 /* Batched gravity (flags SG_GRAV [| SG_POT]) for every system, then each
  * context's acceleration output is refreshed as in sg_compute_accel. */
 sg_status sg_ensemble_gravity(sg_ens *e, uint32_t flags);
 /* One predictor-corrector step of every system (as sg_step), gravity batched.
- * The systems' own launches run on up to 8 side streams of the ensemble
- * (default priority) forked from and joined back into the shared stream;
- * after SG_PREDICT the batched gravity runs beside the systems'
- * neighbours -> density -> SPH(corrector) chains, on a stream of its own
- * (created by sg_ensemble_create with every CU in its mask, so that it
- * holds a hardware queue of its own; the shared stream if that creation
- * fails), forked from the shared stream and joined back into it after the
- * chains are enqueued.  With step_serial (of the first context) the
- * gravity runs on the shared stream before the chains. */
+ * The systems' own launches run on the side streams (system k on stream
+ * k mod nside) forked from and joined back into the shared stream; after
+ * SG_PREDICT the batched gravity runs beside the systems' neighbours ->
+ * density -> SPH(corrector) chains, on the gravity stream (the shared
+ * stream if there is none), forked from the shared stream and joined back
+ * into it after the chains are enqueued.  With step_serial (of the first
+ * context) the gravity runs on the shared stream before the chains. */
 sg_status sg_ensemble_step(sg_ens *e, double dt, uint32_t flags);
 /* nsteps ensemble steps; with use_graph one period of steady-state steps
  * is captured once and replayed (as sg_run).  Waits for the stream. */

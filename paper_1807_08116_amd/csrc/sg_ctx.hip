@@ -135,8 +135,13 @@ bool params_ok(const sg_params* p, const char** why) {
     if (p->cell_scale_log2 < -1 || p->cell_scale_log2 > 1)
         return *why = "cell_scale_log2 must be -1, 0 or 1", false;
     const int v = resolved_variant(*p);
-    if ((p->precision == SG_FP32C || v == 1 || v == 3) && !(p->eps * p->eps >= 1.2e-38))
-        return *why = "FP32 pair arithmetic needs eps^2 in the FP32 normal range", false;
+    if ((v == 1 || v == 3) && !(p->eps * p->eps >= 1.2e-38))
+        return *why = "an FP32-seeded reciprocal square root needs eps^2 in the FP32 normal range", false;
+    // FP32C forms s = (r^2 + eps^2)^(-3/2) in FP32 before the mass multiplies
+    // it (far field); with eps >= 1e-12, s <= 1e36 stays finite, so a
+    // massless padding source adds exactly 0
+    if (p->precision == SG_FP32C && !(p->eps >= 1e-12))
+        return *why = "the FP32C form needs eps >= 1e-12 (finite FP32 (r^2+eps^2)^-1.5)", false;
     if (p->step_serial != 0 && p->step_serial != 1)
         return *why = "step_serial must be 0 or 1", false;
     if (p->grav_reorder < 0 || p->grav_reorder > 1024)
@@ -164,8 +169,10 @@ struct sg_ctx {
     layout L;
     char* ws;
     hipStream_t st;
-    // second stream of a step (gravity beside the neighbour/SPH chain) and
-    // its fork / join events; null when they could not be created
+    // the caller's second stream of a step (gravity beside the
+    // neighbour/SPH chain) and the fork / join events between the two;
+    // null when no second stream was given or the events could not be
+    // created (steps then run their two chains one after the other)
     hipStream_t st2;
     hipEvent_t ev_fork, ev_join;
     // bound state
@@ -584,7 +591,7 @@ size_t sg_workspace_bytes(const sg_params* prm, const sg_caps* caps) {
 }
 
 sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace,
-                    size_t ws_bytes, void* stream, sg_ctx** out) {
+                    size_t ws_bytes, void* stream, void* aux_stream, sg_ctx** out) {
     if (!out) return SG_EINVAL;
     *out = nullptr;
     const char* why = nullptr;
@@ -610,14 +617,15 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
     c->st = (hipStream_t)stream;
     c->st2 = nullptr;
     c->ev_fork = c->ev_join = nullptr;
-    if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-        // without them, steps run their two chains one after the other
-        if (c->st2) (void)hipStreamDestroy(c->st2);
-        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-        c->st2 = nullptr;
-        c->ev_fork = c->ev_join = nullptr;
+    if (aux_stream && aux_stream != stream) {
+        if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+            // without them, steps run their two chains one after the other
+            if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+            c->ev_fork = c->ev_join = nullptr;
+        } else {
+            c->st2 = (hipStream_t)aux_stream;
+        }
     }
     c->bound = false;
     c->ng = c->nh = c->n = 0;
@@ -639,7 +647,6 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
     sg_launch_grid_reset(c->grid(), c->st);
     if (c->check_launch("create") != SG_OK) {
         snprintf(g_create_msg, sizeof(g_create_msg), "%s", c->msg);
-        if (c->st2) (void)hipStreamDestroy(c->st2);
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->ev_join) (void)hipEventDestroy(c->ev_join);
         delete c;
@@ -874,7 +881,7 @@ sg_status sg_export(sg_ctx* c, int32_t what, void* dst, int64_t cap_bytes, int64
     return SG_OK;
 }
 
-sg_status sg_sync(sg_ctx* c, int64_t need[2]) {
+sg_status sg_status_sync(sg_ctx* c, int64_t need[2]) {
     if (!c) return SG_EINVAL;
     if (hipStreamSynchronize(c->st) != hipSuccess) return c->fail(SG_EDEVICE, "stream sync failed");
     sg_grid_dev g;
@@ -903,13 +910,15 @@ sg_status sg_sync(sg_ctx* c, int64_t need[2]) {
 struct sg_ens {
     std::vector<sg_ctx*> c;
     hipStream_t st;
-    // side streams (default priority) that run the systems' own launches
-    // side by side, forked from and joined back into st with events
+    // the caller's side streams that run the systems' own launches side by
+    // side, forked from and joined back into st with events
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> ev;
-    // the batched gravity kernel's own stream (all CUs in its mask, which
-    // gives it a hardware queue of its own) with its fork/join events
+    // the batched gravity kernel's stream with its fork/join events: the
+    // caller's, or one the ensemble creates with every CU in its mask
+    // (which gives it a hardware queue of its own; own_gst)
     hipStream_t gst;
+    bool own_gst;
     hipEvent_t gev[2];
     sg_ens_sys* d_sys;
     sg_ens_task* d_tasks;
@@ -924,9 +933,10 @@ struct sg_ens {
     }
     ~sg_ens() {
         if (st) (void)hipStreamSynchronize(st);
-        for (hipStream_t x : side) (void)hipStreamDestroy(x);
+        for (hipStream_t x : side) (void)hipStreamSynchronize(x);
         for (hipEvent_t x : ev) (void)hipEventDestroy(x);
-        if (gst) (void)hipStreamDestroy(gst);
+        if (gst) (void)hipStreamSynchronize(gst);
+        if (gst && own_gst) (void)hipStreamDestroy(gst);
         for (hipEvent_t x : gev)
             if (x) (void)hipEventDestroy(x);
     }
@@ -1101,14 +1111,18 @@ size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles) {
 }
 
 sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size_t ws_bytes,
+                             void* const* side_streams, int32_t nside, void* grav_stream,
                              sg_ens** out) {
     if (!out || !ctxs || nsys < 1) return SG_EINVAL;
     *out = nullptr;
     if (!d_ws || ((uintptr_t)d_ws & (kAlign - 1))) return SG_EINVAL;
+    if (nside < 0 || nside > 64 || (nside > 0 && !side_streams)) return SG_EINVAL;
     std::vector<sg_ens_sys> sys((size_t)nsys);
     std::vector<std::pair<int64_t, sg_ens_task>> tasks;
     int64_t total = 0;
     if (!ctxs[0] || !ctxs[0]->bound) return SG_EINVAL;
+    for (int32_t i = 0; i < nside; ++i)
+        if (!side_streams[i] || side_streams[i] == (void*)ctxs[0]->st) return SG_EINVAL;
     // launch shape of the first context: 256 * ipl targets per task.  Unset
     // fields take the batched launch's measured best at 64 systems of
     // 8192-262144 particles, 2 targets per lane and 512 sources per tile
@@ -1162,31 +1176,40 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // side streams for the systems' own launches (default priority)
-    const int nside = nsys < 8 ? nsys : 8;
-    for (int i = 0; i < nside; ++i) {
-        hipStream_t x = nullptr;
-        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) break;
-        e->side.push_back(x);
-    }
-    for (size_t i = 0; i < e->side.size() + 1; ++i) {
+    // the caller's side streams for the systems' own launches (at most
+    // one per system is used)
+    const int use_side = nside < nsys ? nside : nsys;
+    for (int i = 0; i < use_side; ++i) e->side.push_back((hipStream_t)side_streams[i]);
+    for (size_t i = 0; i < e->side.size() + 1 && !e->side.empty(); ++i) {
         hipEvent_t x = nullptr;
         if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) break;
         e->ev.push_back(x);
     }
     if (e->ev.size() != e->side.size() + 1) {          // fall back to the shared stream
-        for (hipStream_t x : e->side) (void)hipStreamDestroy(x);
         for (hipEvent_t x : e->ev) (void)hipEventDestroy(x);
         e->side.clear();
         e->ev.clear();
     }
     if (!e->side.empty()) {
-        std::vector<uint32_t> mask((size_t)((cus > 0 ? cus : 256) + 31) / 32, 0xffffffffu);
-        if (cus > 0 && cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
-        if (hipExtStreamCreateWithCUMask(&e->gst, (uint32_t)mask.size(), mask.data()) != hipSuccess ||
+        // the gravity stream: the caller's, else one with every CU in its
+        // mask.  A stream of the runtime's default kind shares one of the
+        // process's few hardware queues with other streams, and a queue
+        // runs its packets in order, so a chain enqueued behind the
+        // persistent gravity kernel in a shared queue would wait for it;
+        // a CU-masked stream gets a hardware queue of its own.
+        e->own_gst = grav_stream == nullptr;
+        if (grav_stream) {
+            e->gst = (hipStream_t)grav_stream;
+        } else {
+            std::vector<uint32_t> mask((size_t)((cus > 0 ? cus : 256) + 31) / 32, 0xffffffffu);
+            if (cus > 0 && cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
+            if (hipExtStreamCreateWithCUMask(&e->gst, (uint32_t)mask.size(), mask.data()) != hipSuccess)
+                e->gst = nullptr;
+        }
+        if (!e->gst ||
             hipEventCreateWithFlags(&e->gev[0], hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&e->gev[1], hipEventDisableTiming) != hipSuccess) {
-            if (e->gst) (void)hipStreamDestroy(e->gst);   // fall back: gravity on st
+            if (e->gst && e->own_gst) (void)hipStreamDestroy(e->gst);   // fall back: gravity on st
             e->gst = nullptr;
             for (hipEvent_t& x : e->gev) {
                 if (x) (void)hipEventDestroy(x);
@@ -1322,7 +1345,6 @@ void sg_destroy(sg_ctx* c) {
     (void)hipStreamSynchronize(c->st);
     if (c->st2) {
         (void)hipStreamSynchronize(c->st2);
-        (void)hipStreamDestroy(c->st2);
         (void)hipEventDestroy(c->ev_fork);
         (void)hipEventDestroy(c->ev_join);
     }

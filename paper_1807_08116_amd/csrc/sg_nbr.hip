@@ -325,7 +325,7 @@ __global__ void k_nbr_check(sg_grid_dev* g, const int64_t* __restrict__ nbr_off,
     const int64_t nnz = nbr_off[ng];
     g->nnz = nnz;
     if (nnz > nnz_cap) {
-        g->err |= SGE_NNZ;
+        atomicOr(&g->err, SGE_NNZ);
         g->need_nnz = nnz;
     }
 }

@@ -338,14 +338,14 @@ __global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap, double cell_scal
             g->org[l][d] = o;
             double span = floor((hi - o) * g->invL[l]);
             if (!(span < 2147483646.0)) {
-                g->err |= SGE_GRID;
+                atomicOr(&g->err, SGE_GRID);
                 g->M = 0;
                 return;
             }
             g->dim[l][d] = (int64_t)span + 1;
             nc *= g->dim[l][d];
             if (nc > 2147483647ll) {
-                g->err |= SGE_GRID;
+                atomicOr(&g->err, SGE_GRID);
                 g->M = 0;
                 return;
             }
@@ -353,14 +353,14 @@ __global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap, double cell_scal
         g->ncell[l] = nc;
         M += nc;
         if (M > 2147483647ll) {
-            g->err |= SGE_GRID;
+            atomicOr(&g->err, SGE_GRID);
             g->M = 0;
             return;
         }
     }
     g->M = M;
     if (M > cell_cap) {
-        g->err |= SGE_CELLS;
+        atomicOr(&g->err, SGE_CELLS);
         g->need_cells = M;
     }
 }

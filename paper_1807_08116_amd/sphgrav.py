@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "SG_OK", 1: "SG_EINVAL", 2: "SG_ECAPACITY", 3: "SG_EDEVICE", 
 # Every entry point declared in include/sphgrav.h.
 EXPORTED = ["sg_workspace_bytes", "sg_create", "sg_bind_state", "sg_build_neighbors",
             "sg_compute_density", "sg_compute_accel", "sg_kick_drift", "sg_step", "sg_run", "sg_cfl_dt", "sg_update_h",
-            "sg_diagnostics", "sg_export", "sg_sync", "sg_profile_enable", "sg_profile_read",
+            "sg_diagnostics", "sg_export", "sg_status_sync", "sg_profile_enable", "sg_profile_read",
             "sg_ensemble_bytes", "sg_ensemble_create", "sg_ensemble_gravity", "sg_ensemble_step",
             "sg_ensemble_run", "sg_ensemble_last_error", "sg_ensemble_destroy",
             "sg_last_error", "sg_destroy", "sg_version"]
@@ -99,7 +99,8 @@ def lib():
     L.sg_workspace_bytes.restype = C.c_size_t
     L.sg_workspace_bytes.argtypes = [C.POINTER(Params), C.POINTER(Caps)]
     L.sg_create.restype = C.c_int
-    L.sg_create.argtypes = [C.POINTER(Params), C.POINTER(Caps), vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.sg_create.argtypes = [C.POINTER(Params), C.POINTER(Caps), vp, C.c_size_t, vp, vp,
+                            C.POINTER(vp)]
     L.sg_bind_state.restype = C.c_int
     L.sg_bind_state.argtypes = [vp, i64, i64, C.POINTER(State)]
     for f in ("sg_build_neighbors", "sg_compute_density"):
@@ -121,8 +122,8 @@ def lib():
     L.sg_diagnostics.argtypes = [vp, vp]
     L.sg_export.restype = C.c_int
     L.sg_export.argtypes = [vp, i32, vp, i64, C.POINTER(i64)]
-    L.sg_sync.restype = C.c_int
-    L.sg_sync.argtypes = [vp, C.POINTER(i64)]
+    L.sg_status_sync.restype = C.c_int
+    L.sg_status_sync.argtypes = [vp, C.POINTER(i64)]
     L.sg_profile_enable.restype = C.c_int
     L.sg_profile_enable.argtypes = [vp, i32]
     L.sg_profile_read.restype = C.c_int
@@ -130,7 +131,8 @@ def lib():
     L.sg_ensemble_bytes.restype = C.c_size_t
     L.sg_ensemble_bytes.argtypes = [i32, i64]
     L.sg_ensemble_create.restype = C.c_int
-    L.sg_ensemble_create.argtypes = [C.POINTER(vp), i32, vp, C.c_size_t, C.POINTER(vp)]
+    L.sg_ensemble_create.argtypes = [C.POINTER(vp), i32, vp, C.c_size_t, C.POINTER(vp), i32, vp,
+                                     C.POINTER(vp)]
     L.sg_ensemble_gravity.restype = C.c_int
     L.sg_ensemble_gravity.argtypes = [vp, u32]
     L.sg_ensemble_step.restype = C.c_int
@@ -171,10 +173,22 @@ def workspace_bytes(params, caps):
     return lib().sg_workspace_bytes(C.byref(params), C.byref(caps))
 
 
-class Context:
-    """One sg_ctx over a torch-allocated workspace on the current stream."""
+def _torch_stream(torch, device, stream):
+    if stream is None:
+        return torch.cuda.current_stream(device)
+    if stream == "new":
+        # a stream of its own (default priority): needed for graph capture
+        return torch.cuda.Stream(device=device)
+    return stream
 
-    def __init__(self, params: Params, caps: Caps, device="cuda", stream=None):
+
+class Context:
+    """One sg_ctx over a torch-allocated workspace on a torch stream (the
+    current one by default), with a second torch stream for the gravity
+    beside the neighbour/SPH chain of a step (aux_stream: "new" by default,
+    None for none)."""
+
+    def __init__(self, params: Params, caps: Caps, device="cuda", stream=None, aux_stream="new"):
         import torch
         self.torch = torch
         self.params = params
@@ -188,16 +202,15 @@ class Context:
         base = self.ws_raw.data_ptr()
         self.ws_ptr = (base + 255) & ~255
         self.ws_bytes = nbytes
-        if stream is None:
-            stream = torch.cuda.current_stream(self.device)
-        elif stream == "new":
-            # a stream of its own (default priority): needed for graph capture
-            stream = torch.cuda.Stream(device=self.device)
+        stream = _torch_stream(torch, self.device, stream)
+        aux = None if aux_stream is None else _torch_stream(torch, self.device, aux_stream)
         torch.cuda.synchronize(self.device)     # state uploads on other streams are done
         self.stream = stream
+        self.aux_stream = aux
         h = C.c_void_p()
         rc = L.sg_create(C.byref(params), C.byref(caps), C.c_void_p(self.ws_ptr),
-                         C.c_size_t(nbytes), C.c_void_p(stream.cuda_stream), C.byref(h))
+                         C.c_size_t(nbytes), C.c_void_p(stream.cuda_stream),
+                         C.c_void_p(aux.cuda_stream if aux is not None else None), C.byref(h))
         if rc != SG_OK:
             raise SGError(rc, "sg_create failed: " + L.sg_last_error(None).decode())
         self.h = h
@@ -285,7 +298,7 @@ class Context:
     def sync(self):
         """Wait for the stream; raise SGError (with .need) on a device-side error."""
         need = (C.c_int64 * 2)()
-        rc = lib().sg_sync(self.h, need)
+        rc = lib().sg_status_sync(self.h, need)
         if rc != SG_OK:
             e = SGError(rc, lib().sg_last_error(self.h).decode())
             e.need = (int(need[0]), int(need[1]))
@@ -365,7 +378,7 @@ class Engine:
     """Convenience owner of a context plus a bound state, with capacity retry."""
 
     def __init__(self, st: dict, precision=SG_FP64, device="cuda", params=None, caps=None,
-                 with_pot=True, stream=None, **kw):
+                 with_pot=True, stream=None, aux_stream="new", **kw):
         self.ng = int(st["ng"])
         self.n = len(st["x"])
         self.nh = self.n - self.ng
@@ -374,10 +387,12 @@ class Engine:
         self.dev = to_device(st, device, with_pot=with_pot)
         self.device = device
         self.stream = stream
+        self.aux_stream = aux_stream
         self._make()
 
     def _make(self):
-        self.ctx = Context(self.params, self.caps, self.device, stream=self.stream)
+        self.ctx = Context(self.params, self.caps, self.device, stream=self.stream,
+                           aux_stream=self.aux_stream)
         if self.stream == "new":
             self.stream = self.ctx.stream
         self.ctx.bind_state(self.dev, self.ng, self.nh)
@@ -414,9 +429,19 @@ class Ensemble:
     def __init__(self, states, device="cuda", **kw):
         import torch
         self.torch = torch
-        self.stream = torch.cuda.Stream(device=torch.device(device))
-        self.engines = [Engine(st, precision=SG_FP32C, device=device, stream=self.stream, **kw)
-                        for st in states]
+        dev = torch.device(device)
+        self.stream = torch.cuda.Stream(device=dev)
+        # the systems' own launches run side by side on up to 8 torch
+        # streams (distinct from the shared one); the batched gravity gets
+        # the library's CU-masked stream (grav_stream NULL)
+        self.side = []
+        for _ in range(min(8, len(states))):
+            x = torch.cuda.Stream(device=dev)
+            if x.cuda_stream != self.stream.cuda_stream and all(
+                    x.cuda_stream != y.cuda_stream for y in self.side):
+                self.side.append(x)
+        self.engines = [Engine(st, precision=SG_FP32C, device=device, stream=self.stream,
+                               aux_stream=None, **kw) for st in states]
         total = sum(e.n for e in self.engines)
         L = lib()
         nbytes = L.sg_ensemble_bytes(len(self.engines), total)
@@ -425,7 +450,9 @@ class Ensemble:
         handles = (C.c_void_p * len(self.engines))(*[e.ctx.h.value for e in self.engines])
         h = C.c_void_p()
         torch.cuda.synchronize()
-        rc = L.sg_ensemble_create(handles, len(self.engines), C.c_void_p(ptr), nbytes, C.byref(h))
+        side = (C.c_void_p * max(1, len(self.side)))(*[x.cuda_stream for x in self.side])
+        rc = L.sg_ensemble_create(handles, len(self.engines), C.c_void_p(ptr), nbytes, side,
+                                  len(self.side), None, C.byref(h))
         if rc != SG_OK:
             raise SGError(rc, "sg_ensemble_create failed")
         self.h = h

@@ -59,6 +59,7 @@ def test_workspace_validation(sg):
                 dict(G=float("nan")), dict(grav_variant=5), dict(grav_variant=3, eps=1e-20),
                 dict(grav_variant=1, eps=1e-20),
                 dict(precision=1, grav_variant=2), dict(precision=1, eps=1e-20),
+                dict(precision=1, eps=9e-13),
                 dict(grav_tile=64), dict(grav_tile=1024), dict(cell_scale_log2=2),
                 dict(cell_scale_log2=-2), dict(step_serial=2), dict(step_serial=-1),
                 dict(grav_reorder=-1), dict(grav_reorder=1025)):
@@ -66,6 +67,7 @@ def test_workspace_validation(sg):
     for ok in (dict(grav_tile=128), dict(grav_tile=512), dict(cell_scale_log2=-1),
                dict(cell_scale_log2=1), dict(grav_variant=2, eps=1e-20),
                dict(grav_variant=3), dict(grav_variant=4, eps=1e-20), dict(eps=1e-20),
+               dict(precision=1, eps=1e-12),
                dict(step_serial=1), dict(grav_reorder=1), dict(grav_reorder=1024)):
         assert sg.workspace_bytes(sg.make_params(**ok), caps) > 0, ok
     # the diagnostics slot of a captured chunk grows from 80 bytes (one
@@ -87,16 +89,17 @@ def test_create_rejects_before_device(sg):
     p, c = sg.make_params(), sg.default_caps(100, 100)
     h = C.c_void_p()
     need = sg.workspace_bytes(p, c)
-    assert L.sg_create(C.byref(p), C.byref(c), None, need, None, C.byref(h)) == sg.SG_EINVAL
-    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x1001), need, None, C.byref(h)) == sg.SG_EINVAL
-    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x100000), need - 1, None,
+    assert L.sg_create(C.byref(p), C.byref(c), None, need, None, None, C.byref(h)) == sg.SG_EINVAL
+    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x1001), need, None, None, C.byref(h)) == sg.SG_EINVAL
+    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x100000), need - 1, None, None,
                        C.byref(h)) == sg.SG_EINVAL
-    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x100000), need, None, None) == sg.SG_EINVAL
+    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x100000), need, None, None,
+                       None) == sg.SG_EINVAL
     assert h.value is None
-    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x1001), need, None, C.byref(h)) == sg.SG_EINVAL
+    assert L.sg_create(C.byref(p), C.byref(c), C.c_void_p(0x1001), need, None, None, C.byref(h)) == sg.SG_EINVAL
     assert L.sg_bind_state(None, 1, 1, None) == sg.SG_EINVAL
     assert L.sg_build_neighbors(None) == sg.SG_EINVAL
-    assert L.sg_sync(None, None) == sg.SG_EINVAL
+    assert L.sg_status_sync(None, None) == sg.SG_EINVAL
     assert b"aligned" in L.sg_last_error(None)         # reason of the last failed create
     assert L.sg_version().startswith(b"sphgrav")
 
@@ -119,4 +122,12 @@ def test_ensemble_bytes(sg):
     L = sg.lib()
     assert L.sg_ensemble_bytes(0, 100) == 0
     assert L.sg_ensemble_bytes(64, 4659360) > 64 * 8
-    assert L.sg_ensemble_create(None, 0, None, 0, None) == sg.SG_EINVAL
+    assert L.sg_ensemble_create(None, 0, None, 0, None, 0, None, None) == sg.SG_EINVAL
+    # side streams: a count without an array, or a negative count
+    dummy = (C.c_void_p * 1)(0x1000)
+    out = C.c_void_p()
+    assert L.sg_ensemble_create(dummy, 1, C.c_void_p(0x100000), 1 << 20, None, 2, None,
+                                C.byref(out)) == sg.SG_EINVAL
+    assert L.sg_ensemble_create(dummy, 1, C.c_void_p(0x100000), 1 << 20, dummy, -1, None,
+                                C.byref(out)) == sg.SG_EINVAL
+    assert out.value is None

@@ -47,6 +47,55 @@ def test_graph_steps_bitwise_equal_eager(sg, c0, form):
     assert abs(h_e[-1, 3] - h_e[0, 3]) < 1e-3 * abs(h_e[0, 3])
 
 
+@pytest.fixture(scope="module")
+def c0_full():
+    from paper_1807_08116_amd import ic
+    return ic.make("c0")
+
+
+# Bounds of a graph-captured run of 6 steps against the oracle's
+# predictor-corrector.  FP64: only summation order differs.  FP32C: the
+# accelerations carry a normwise error of about 2e-7; over k steps of dt it
+# moves velocities by about k dt |da| and positions by about k dt^2 |da|
+# (measured on one MI355X: FP64 x 2.5e-18, v 3.9e-17, e 3.0e-17, E 1.4e-16;
+# FP32C x 7.9e-13, v 2.9e-9, e 1.5e-9, E 3.3e-8).
+GRAPH_ORACLE_TOL = {"fp64": {"x": 1e-12, "v": 1e-12, "e": 1e-12, "E": 1e-12},
+                    "fp32c": {"x": 1e-10, "v": 3e-8, "e": 1e-8, "E": 1e-6}}
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+def test_graph_steps_match_oracle(sg, orc, c0_full, form):
+    # sg_run with a captured step (1 eager step + 5 replays) against the
+    # oracle's predictor-corrector (Sec. 2.2) on the full 4096 + 4096
+    # workload: positions, velocities, energies and the conserved sums.
+    from paper_1807_08116_amd import ic
+    prm = ic.DEFAULT_PARAMS
+    p = sg.SG_FP64 if form == "fp64" else sg.SG_FP32C
+    tol = GRAPH_ORACLE_TOL[form]
+    dt, nsteps = 2e-3, 6
+    eng = sg.Engine(c0_full, precision=p, stream="new")
+    hist = eng.ctx.run(dt, nsteps, sg.SG_POT, use_graph=True).cpu().numpy()
+    st, cache = c0_full, None
+    for _ in range(nsteps):
+        st, cache = orc.pc_step(st, prm, dt, cache)
+    ng = st["ng"]
+
+    def err(a, b):
+        return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
+
+    ex = err(np.stack([eng.numpy(f) for f in ("x", "y", "z")]),
+             np.stack([st[f] for f in ("x", "y", "z")]))
+    ev = err(np.stack([eng.numpy(f) for f in ("vx", "vy", "vz")]),
+             np.stack([st[f] for f in ("vx", "vy", "vz")]))
+    ee = err(eng.numpy("e")[:ng], st["e"])
+    d = orc.diagnostics(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["m"],
+                        st["e"], cache["pot"], ng)
+    eE = abs(hist[-1, 3] - d[3]) / abs(d[3])
+    print(form, "graph run vs oracle after %d steps: x %.2e v %.2e e %.2e E %.2e"
+          % (nsteps, ex, ev, ee, eE))
+    assert ex < tol["x"] and ev < tol["v"] and ee < tol["e"] and eE < tol["E"]
+
+
 def test_graph_replays_with_eager_work_between(sg, c0):
     dt = 2e-3
     ref = sg.Engine(c0, precision=sg.SG_FP64, stream="new")
