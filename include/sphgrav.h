@@ -167,6 +167,29 @@ size_t sg_workspace_bytes(const sg_params *prm, const sg_caps *caps);
 sg_status sg_create(const sg_params *prm, const sg_caps *caps, void *d_workspace,
                     size_t ws_bytes, void *stream, void *aux_stream, sg_ctx **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): sg_create with
+ * the library's own workspace instead of a caller-owned one.  The
+ * workspace is a device array of SG_STATIC_WS_BYTES bytes inside the
+ * library, one per GPU (the current device at the call), held until the
+ * process ends; this call allocates nothing (no hipMalloc, no host heap,
+ * no stream or event).  At most one such context may exist per GPU at a
+ * time (SG_ESTATE otherwise; sg_destroy frees the slot), since all of them
+ * would share that array, which keeps the last context's contents: the
+ * status word and grid record are cleared here, and everything else is
+ * written before it is read.  Calls on it that overlap (from several host
+ * threads) race.
+ * SG_ECAPACITY, with a message, when sg_workspace_bytes(prm, caps) exceeds
+ * SG_STATIC_WS_BYTES (64 MiB: with the Python binding's default
+ * capacities, up to 11939 gas + 11939 halo particles); SG_EINVAL as
+ * sg_create for bad parameters.  Steps run the gravity and the
+ * neighbour/SPH chain one after the other on `stream` (no auxiliary
+ * stream).  Every other entry point works on the context as on one from
+ * sg_create. */
+#define SG_STATIC_WS_BYTES (64ull << 20)
+sg_status sg_create_static(const sg_params *prm, const sg_caps *caps, void *stream,
+                           sg_ctx **out);
+
 /* Bind a particle state (the "upload" step: the state already sits in
  * device memory owned by the caller).  n_gas <= n_gas_cap, n_halo <=
  * n_halo_cap, n_gas + n_halo >= 1.  Invalidates cached neighbours, density

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -189,6 +190,10 @@ struct sg_ctx {
     bool have_order;
     int32_t order_age;
     char msg[256];
+    // made by sg_create_static: lives in the per-device slot below, over the
+    // library's own device array (device index `dev`)
+    bool is_static;
+    int dev;
     // stage timing
     bool prof;
     struct mark {
@@ -580,6 +585,96 @@ sg_status do_diag(sg_ctx* c, double* d_out10) {
     return c->check_launch("diagnostics");
 }
 
+// Everything sg_create and sg_create_static share: fields, the cleared
+// status word and grid record (the workspace may hold anything).
+sg_status init_ctx(sg_ctx* c, const sg_params* prm, const sg_caps* caps, const layout& L,
+                   char* ws, hipStream_t stream) {
+    c->prm = *prm;
+    c->caps = *caps;
+    c->L = L;
+    c->ws = ws;
+    c->st = stream;
+    c->bound = false;
+    c->ng = c->nh = c->n = 0;
+    memset(&c->s, 0, sizeof(c->s));
+    c->invalidate_positions();
+    c->have_order = false;
+    c->order_age = 0;
+    c->predicted = false;
+    c->accel_after_predict = false;
+    c->beside_grav = false;
+    c->msg[0] = 0;
+    c->prof = false;
+    c->open_ev = nullptr;
+    c->open_stage = 0;
+    for (int k = 0; k < SG_NSTAGE; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    (void)hipGetLastError();            // drop a stale error of an earlier call
+    sg_launch_status_clear(c->grid(), c->st);
+    sg_launch_grid_reset(c->grid(), c->st);
+    return c->check_launch("create");
+}
+
+}  // namespace
+
+// ------------------------------------------------ allocation-free contexts --
+// The workspace of contexts made by sg_create_static: one file-scope device
+// array, of which the runtime gives every GPU the library runs on its own
+// copy, held until the process ends.  Host code never passes the array's
+// name to the GPU (on the host it only stands for the symbol): its device
+// address on the current GPU comes from hipGetSymbolAddress, once per
+// device, and only that address is used.
+static __device__ __attribute__((aligned(256))) char scratch[SG_STATIC_WS_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char* g_static_ptr[kMaxDevices];      // device address of `scratch`, per device
+bool g_static_live[kMaxDevices];      // a static context exists on the device
+sg_ctx g_static_ctx[kMaxDevices];     // its host record (no allocation)
+
+// Claim the current device's array (its address resolved on first use).
+sg_status static_acquire(int* dev_out, char** ws_out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        snprintf(g_create_msg, sizeof(g_create_msg), "no current HIP device");
+        return SG_EDEVICE;
+    }
+    if (dev >= kMaxDevices) {
+        snprintf(g_create_msg, sizeof(g_create_msg), "device index beyond %d", kMaxDevices - 1);
+        return SG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_live[dev]) {
+        snprintf(g_create_msg, sizeof(g_create_msg),
+                 "a static context already exists on device %d (destroy it first)", dev);
+        return SG_ESTATE;
+    }
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            snprintf(g_create_msg, sizeof(g_create_msg), "hipGetSymbolAddress: %s",
+                     hipGetErrorString(e));
+            (void)hipGetLastError();
+            return SG_EDEVICE;
+        }
+        g_static_ptr[dev] = (char*)p;
+    }
+    g_static_live[dev] = true;
+    *dev_out = dev;
+    *ws_out = g_static_ptr[dev];
+    return SG_OK;
+}
+
+void static_release(int dev) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_live[dev] = false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -610,13 +705,8 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
     }
     sg_ctx* c = new (std::nothrow) sg_ctx();
     if (!c) return SG_EINVAL;
-    c->prm = *prm;
-    c->caps = *caps;
-    c->L = L;
-    c->ws = (char*)d_workspace;
-    c->st = (hipStream_t)stream;
-    c->st2 = nullptr;
     c->ev_fork = c->ev_join = nullptr;
+    c->st2 = nullptr;
     if (aux_stream && aux_stream != stream) {
         if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -627,29 +717,45 @@ sg_status sg_create(const sg_params* prm, const sg_caps* caps, void* d_workspace
             c->st2 = (hipStream_t)aux_stream;
         }
     }
-    c->bound = false;
-    c->ng = c->nh = c->n = 0;
-    memset(&c->s, 0, sizeof(c->s));
-    c->invalidate_positions();
-    c->have_order = false;
-    c->predicted = false;
-    c->accel_after_predict = false;
-    c->msg[0] = 0;
-    c->prof = false;
-    c->open_ev = nullptr;
-    c->open_stage = 0;
-    for (int k = 0; k < SG_NSTAGE; ++k) {
-        c->prof_ms[k] = 0.0;
-        c->prof_n[k] = 0;
-    }
-    (void)hipGetLastError();            // drop a stale error of an earlier call
-    sg_launch_status_clear(c->grid(), c->st);
-    sg_launch_grid_reset(c->grid(), c->st);
-    if (c->check_launch("create") != SG_OK) {
+    if (init_ctx(c, prm, caps, L, (char*)d_workspace, (hipStream_t)stream) != SG_OK) {
         snprintf(g_create_msg, sizeof(g_create_msg), "%s", c->msg);
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->ev_join) (void)hipEventDestroy(c->ev_join);
         delete c;
+        return SG_EDEVICE;
+    }
+    *out = c;
+    return SG_OK;
+}
+
+sg_status sg_create_static(const sg_params* prm, const sg_caps* caps, void* stream,
+                           sg_ctx** out) {
+    if (!out) return SG_EINVAL;
+    *out = nullptr;
+    const char* why = nullptr;
+    if (!params_ok(prm, &why) || !caps_ok(caps, &why)) {
+        snprintf(g_create_msg, sizeof(g_create_msg), "%s", why ? why : "invalid arguments");
+        return SG_EINVAL;
+    }
+    const layout L = make_layout(prm, caps);
+    if (L.total > (size_t)SG_STATIC_WS_BYTES) {
+        snprintf(g_create_msg, sizeof(g_create_msg),
+                 "workspace of %zu bytes for these capacities exceeds the static array (%llu bytes)",
+                 L.total, (unsigned long long)SG_STATIC_WS_BYTES);
+        return SG_ECAPACITY;
+    }
+    char* ws = nullptr;
+    int dev = -1;
+    sg_status r = static_acquire(&dev, &ws);
+    if (r != SG_OK) return r;
+    sg_ctx* c = &g_static_ctx[dev];
+    c->st2 = nullptr;                 // one stream, no events: steps run in order
+    c->ev_fork = c->ev_join = nullptr;
+    c->is_static = true;
+    c->dev = dev;
+    if (init_ctx(c, prm, caps, L, ws, (hipStream_t)stream) != SG_OK) {
+        snprintf(g_create_msg, sizeof(g_create_msg), "%s", c->msg);
+        static_release(dev);
         return SG_EDEVICE;
     }
     *out = c;
@@ -1353,6 +1459,13 @@ void sg_destroy(sg_ctx* c) {
         (void)hipEventDestroy(mk.b);
     }
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    if (c->is_static) {               // the slot and the array stay for the next one
+        c->marks.clear();
+        c->pool.clear();
+        c->bound = false;
+        static_release(c->dev);
+        return;
+    }
     delete c;
 }
 

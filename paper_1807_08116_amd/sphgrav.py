@@ -23,6 +23,7 @@ SG_FP64, SG_FP32C = 0, 1
 SG_SPH, SG_GRAV, SG_POT = 1, 2, 4
 SG_PREDICT, SG_CORRECT = 0, 1
 SG_MAX_LEVELS = 16
+SG_STATIC_WS_BYTES = 64 << 20
 (SG_X_KEYS, SG_X_COUNTS, SG_X_OFFSETS, SG_X_HMAX, SG_X_PERM, SG_X_NBR_OFF, SG_X_NBR_IDX,
  SG_X_GRID, SG_X_GORDER, SG_X_ACC_SPH, SG_X_ACC_GRAV) = range(11)
 
@@ -30,7 +31,7 @@ STATUS_NAMES = {0: "SG_OK", 1: "SG_EINVAL", 2: "SG_ECAPACITY", 3: "SG_EDEVICE", 
                 5: "SG_ENONFINITE", 6: "SG_ERANGE"}
 
 # Every entry point declared in include/sphgrav.h.
-EXPORTED = ["sg_workspace_bytes", "sg_create", "sg_bind_state", "sg_build_neighbors",
+EXPORTED = ["sg_workspace_bytes", "sg_create", "sg_create_static", "sg_bind_state", "sg_build_neighbors",
             "sg_compute_density", "sg_compute_accel", "sg_kick_drift", "sg_step", "sg_run", "sg_cfl_dt", "sg_update_h",
             "sg_diagnostics", "sg_export", "sg_status_sync", "sg_profile_enable", "sg_profile_read",
             "sg_ensemble_bytes", "sg_ensemble_create", "sg_ensemble_gravity", "sg_ensemble_step",
@@ -101,6 +102,8 @@ def lib():
     L.sg_create.restype = C.c_int
     L.sg_create.argtypes = [C.POINTER(Params), C.POINTER(Caps), vp, C.c_size_t, vp, vp,
                             C.POINTER(vp)]
+    L.sg_create_static.restype = C.c_int
+    L.sg_create_static.argtypes = [C.POINTER(Params), C.POINTER(Caps), vp, C.POINTER(vp)]
     L.sg_bind_state.restype = C.c_int
     L.sg_bind_state.argtypes = [vp, i64, i64, C.POINTER(State)]
     for f in ("sg_build_neighbors", "sg_compute_density"):
@@ -188,13 +191,28 @@ class Context:
     beside the neighbour/SPH chain of a step (aux_stream: "new" by default,
     None for none)."""
 
-    def __init__(self, params: Params, caps: Caps, device="cuda", stream=None, aux_stream="new"):
+    def __init__(self, params: Params, caps: Caps, device="cuda", stream=None, aux_stream="new",
+                 static=False):
         import torch
         self.torch = torch
         self.params = params
         self.caps = caps
         self.device = torch.device(device)
         L = lib()
+        if static:
+            # sg_create_static: the library's own workspace, no aux stream
+            stream = _torch_stream(torch, self.device, stream)
+            torch.cuda.synchronize(self.device)
+            self.stream, self.aux_stream = stream, None
+            h = C.c_void_p()
+            with torch.cuda.device(self.device):
+                rc = L.sg_create_static(C.byref(params), C.byref(caps),
+                                        C.c_void_p(stream.cuda_stream), C.byref(h))
+            if rc != SG_OK:
+                raise SGError(rc, "sg_create_static failed: " + L.sg_last_error(None).decode())
+            self.h = h
+            self.state = None
+            return
         nbytes = L.sg_workspace_bytes(C.byref(params), C.byref(caps))
         if nbytes == 0:
             raise SGError(SG_EINVAL, "invalid parameters or capacities")
@@ -378,7 +396,7 @@ class Engine:
     """Convenience owner of a context plus a bound state, with capacity retry."""
 
     def __init__(self, st: dict, precision=SG_FP64, device="cuda", params=None, caps=None,
-                 with_pot=True, stream=None, aux_stream="new", **kw):
+                 with_pot=True, stream=None, aux_stream="new", static=False, **kw):
         self.ng = int(st["ng"])
         self.n = len(st["x"])
         self.nh = self.n - self.ng
@@ -388,11 +406,12 @@ class Engine:
         self.device = device
         self.stream = stream
         self.aux_stream = aux_stream
+        self.static = static
         self._make()
 
     def _make(self):
         self.ctx = Context(self.params, self.caps, self.device, stream=self.stream,
-                           aux_stream=self.aux_stream)
+                           aux_stream=self.aux_stream, static=self.static)
         if self.stream == "new":
             self.stream = self.ctx.stream
         self.ctx.bind_state(self.dev, self.ng, self.nh)

@@ -101,6 +101,15 @@ def test_create_rejects_before_device(sg):
     assert L.sg_build_neighbors(None) == sg.SG_EINVAL
     assert L.sg_status_sync(None, None) == sg.SG_EINVAL
     assert b"aligned" in L.sg_last_error(None)         # reason of the last failed create
+    # the allocation-free variant checks its arguments and its size bound
+    # before touching a device
+    assert L.sg_create_static(C.byref(p), C.byref(c), None, None) == sg.SG_EINVAL
+    bad = sg.make_params(eps=0.0)
+    assert L.sg_create_static(C.byref(bad), C.byref(c), None, C.byref(h)) == sg.SG_EINVAL
+    big = sg.default_caps(100000, 100000)
+    assert sg.workspace_bytes(p, big) > sg.SG_STATIC_WS_BYTES
+    assert L.sg_create_static(C.byref(p), C.byref(big), None, C.byref(h)) == sg.SG_ECAPACITY
+    assert h.value is None and b"exceeds the static array" in L.sg_last_error(None)
     assert L.sg_version().startswith(b"sphgrav")
 
 
