@@ -329,37 +329,37 @@ sg_status sg_status_sync(sg_ctx *ctx, int64_t need[2]);
  * (system, block of 256 * grav_ipl targets) tasks, largest systems first,
  * from a device counter until none is left; grav_ipl and grav_tile are
  * those of the first context, 0 selecting 2 targets per lane and 512
- * sources per tile for this launch.
+ * sources per tile for this launch.  The per-particle stages of a step
+ * (the predictor's SPH pass, the combination of the SPH and gravity parts,
+ * predictor and corrector, the Morton order and sorted copies of the
+ * gravity inputs) also run as one launch each for all systems; only the
+ * corrector's neighbour build, density and SPH pass run system by system,
+ * beside the gravity kernel.
  * The ensemble keeps pointers into the contexts: do not rebind or destroy
  * them while it exists.  d_ws: caller-owned device memory of
- * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task
- * table is uploaded once, synchronously, by sg_ensemble_create.
- * side_streams[0..nside): caller-owned streams (none equal to the
- * contexts' stream; nside <= 64, at most nsys used) on which the systems'
- * own launches run side by side; nside = 0 runs everything on the shared
- * stream.  grav_stream: the caller's stream for the batched gravity beside
- * those launches, or NULL: then, if side streams are given, the ensemble
- * creates (and destroys) one stream with every CU in its mask, because a
- * stream of that kind gets a hardware queue of its own, where an ordinary
- * stream may share a queue with a side stream and hold that side stream's
- * launches behind the long gravity kernel.  Every stream must outlive the
- * ensemble. */
+ * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task and
+ * system tables are uploaded once, synchronously, by sg_ensemble_create.
+ * grav_stream: the caller's stream (not the contexts' stream) for the
+ * batched gravity beside the systems' corrector chains, or NULL: then the
+ * ensemble creates (and destroys) one stream with every CU in its mask,
+ * because a stream of that kind gets a hardware queue of its own, where an
+ * ordinary stream may share a queue with the contexts' stream and hold the
+ * chains' launches behind the long gravity kernel.  The stream must
+ * outlive the ensemble. */
 typedef struct sg_ens sg_ens;   /* opaque */
 size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles);
 sg_status sg_ensemble_create(sg_ctx *const *ctxs, int32_t nsys, void *d_ws, size_t ws_bytes,
-                             void *const *side_streams, int32_t nside, void *grav_stream,
-                             sg_ens **out);
+                             void *grav_stream, sg_ens **out);
 /* Batched gravity (flags SG_GRAV [| SG_POT]) for every system, then each
  * context's acceleration output is refreshed as in sg_compute_accel. */
 sg_status sg_ensemble_gravity(sg_ens *e, uint32_t flags);
-/* One predictor-corrector step of every system (as sg_step), gravity batched.
- * The systems' own launches run on the side streams (system k on stream
- * k mod nside) forked from and joined back into the shared stream; after
- * SG_PREDICT the batched gravity runs beside the systems' neighbours ->
- * density -> SPH(corrector) chains, on the gravity stream (the shared
- * stream if there is none), forked from the shared stream and joined back
- * into it after the chains are enqueued.  With step_serial (of the first
- * context) the gravity runs on the shared stream before the chains. */
+/* One predictor-corrector step of every system (as sg_step), gravity
+ * batched, on the contexts' stream; after SG_PREDICT the batched gravity
+ * runs on the gravity stream, forked from the contexts' stream and joined
+ * back into it, beside the systems' neighbours -> density ->
+ * SPH(corrector) chains.  With step_serial (of the first context) the
+ * gravity runs on the contexts' stream before the chains.  Results equal
+ * those of sg_step on each context alone (same launch shape) bit for bit. */
 sg_status sg_ensemble_step(sg_ens *e, double dt, uint32_t flags);
 /* nsteps ensemble steps; with use_graph one period of steady-state steps
  * is captured once and replayed (as sg_run).  Waits for the stream. */

@@ -1016,10 +1016,6 @@ sg_status sg_status_sync(sg_ctx* c, int64_t need[2]) {
 struct sg_ens {
     std::vector<sg_ctx*> c;
     hipStream_t st;
-    // the caller's side streams that run the systems' own launches side by
-    // side, forked from and joined back into st with events
-    std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> ev;
     // the batched gravity kernel's stream with its fork/join events: the
     // caller's, or one the ensemble creates with every CU in its mask
     // (which gives it a hardware queue of its own; own_gst)
@@ -1032,6 +1028,7 @@ struct sg_ens {
     int32_t ntasks;
     int nblocks, ipl, tile;
     double eps, G;
+    sg_seg seg;                  // segmented launches over all systems
     char msg[256];
     sg_status fail(sg_status code, const char* m) {
         snprintf(msg, sizeof(msg), "%s", m);
@@ -1039,8 +1036,6 @@ struct sg_ens {
     }
     ~sg_ens() {
         if (st) (void)hipStreamSynchronize(st);
-        for (hipStream_t x : side) (void)hipStreamSynchronize(x);
-        for (hipEvent_t x : ev) (void)hipEventDestroy(x);
         if (gst) (void)hipStreamSynchronize(gst);
         if (gst && own_gst) (void)hipStreamDestroy(gst);
         for (hipEvent_t x : gev)
@@ -1048,73 +1043,52 @@ struct sg_ens {
     }
 };
 
-extern "C++" {  // the helpers below are templates
+extern "C++" {
 namespace {
 
-size_t ens_layout(int32_t nsys, int64_t ntasks, size_t* o_tasks, size_t* o_counter) {
-    size_t o = al(sizeof(sg_ens_sys) * (size_t)nsys);
-    *o_tasks = o;
-    o += al(sizeof(sg_ens_task) * (size_t)(ntasks > 0 ? ntasks : 1));
-    *o_counter = o;
-    o += al(sizeof(int32_t));
+struct ens_offsets {
+    size_t tasks, counter, seg, pfx, total;
+};
+
+ens_offsets ens_layout(int32_t nsys, int64_t ntasks) {
+    ens_offsets o;
+    size_t at = al(sizeof(sg_ens_sys) * (size_t)nsys);
+    o.tasks = at;
+    at += al(sizeof(sg_ens_task) * (size_t)(ntasks > 0 ? ntasks : 1));
+    o.counter = at;
+    at += al(sizeof(int32_t));
+    o.seg = at;
+    at += al(sizeof(sg_seg_sys) * (size_t)nsys);
+    o.pfx = at;
+    at += al(sizeof(int64_t) * SG_SEG_NPFX * (size_t)(nsys + 1));
+    o.total = at;
     return o;
 }
 
-// Run fn(c) for every system: system k on side stream k mod K, all side
-// streams forked from the shared stream and joined back into it (also while
-// the shared stream is being captured into a graph: the side streams then
-// join the capture).  shared() enqueues work on the shared stream right
-// after the fork, so that it runs beside the systems' work.  Without side
-// streams, everything in order on the shared stream.
-template <typename S, typename F>
-sg_status ens_fork_join(sg_ens* e, S&& shared, F&& fn) {
-    const int K = (int)e->side.size();
-    if (K == 0) {
-        sg_status r = shared();
-        if (r != SG_OK) return r;
-        for (sg_ctx* c : e->c) {
-            r = fn(c);
-            if (r != SG_OK) return e->fail(r, c->msg);
+// Morton order (when due) and sorted copies of every system, in segmented
+// launches on the shared stream.  The systems of an ensemble normally share
+// the schedule of the order; a system whose schedule differs (it was
+// stepped on its own) gets its own sort.
+sg_status ens_grav_prep(sg_ens* e) {
+    sg_ctx* c0 = e->c[0];
+    c0->begin(SG_ST_GRAV_PREP);
+    bool all = true;
+    for (sg_ctx* c : e->c) all = all && sorts_next(c);
+    if (all) sg_seg_launch_morton_order(e->seg, e->st);
+    for (sg_ctx* c : e->c) {
+        if (sorts_next(c)) {
+            if (!all)
+                sg_launch_morton_order(c->s.x, c->s.y, c->s.z, c->n, c->grid(),
+                                       c->at<int32_t>(c->L.gorder), c->at<void>(c->L.morton), e->st);
+            c->have_order = true;
+            c->order_age = 0;
         }
-        return SG_OK;
+        ++c->order_age;
     }
-    if (hipEventRecord(e->ev[0], e->st) != hipSuccess) return e->fail(SG_EDEVICE, "fork: event record failed");
-    for (int i = 0; i < K; ++i)
-        if (hipStreamWaitEvent(e->side[i], e->ev[0], 0) != hipSuccess)
-            return e->fail(SG_EDEVICE, "fork: stream wait failed");
-    sg_status rc = shared();
-    char why[256] = "";
-    if (rc != SG_OK) snprintf(why, sizeof(why), "%s", e->msg);
-    for (size_t k = 0; k < e->c.size() && rc == SG_OK; ++k) {
-        sg_ctx* c = e->c[k];
-        hipStream_t own = c->st;
-        c->st = e->side[k % K];
-        rc = fn(c);
-        c->st = own;
-        if (rc != SG_OK) snprintf(why, sizeof(why), "%s", c->msg);
-    }
-    // join every side stream (also after an error, so a capture stays whole)
-    for (int i = 0; i < K; ++i) {
-        const bool ok = hipEventRecord(e->ev[i + 1], e->side[i]) == hipSuccess &&
-                        hipStreamWaitEvent(e->st, e->ev[i + 1], 0) == hipSuccess;
-        if (!ok && rc == SG_OK) {
-            rc = SG_EDEVICE;
-            snprintf(why, sizeof(why), "join: event record or stream wait failed");
-        }
-    }
-    return rc == SG_OK ? SG_OK : e->fail(rc, why);
-}
-
-template <typename F>
-sg_status ens_each(sg_ens* e, F&& fn) {
-    return ens_fork_join(e, [] { return SG_OK; }, fn);
-}
-
-// Morton order, sorted copies and boxes of one system (its gravity inputs).
-sg_status ens_grav_prep(sg_ctx* c, bool pot) {
-    sg_grav_args a;
-    grav_args(c, pot, a);
-    return grav_prep(c, a);
+    sg_seg_launch_grav_sorted(e->seg, e->st);
+    c0->end();
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? SG_OK : e->fail(SG_EDEVICE, hipGetErrorString(err));
 }
 
 // The batched gravity launch on stream st (inputs prepared; stage timing
@@ -1138,73 +1112,132 @@ sg_status ens_grav_launch(sg_ens* e, bool pot, hipStream_t st) {
 }
 
 sg_status ens_gravity(sg_ens* e, bool pot) {
-    sg_status r = ens_each(e, [&](sg_ctx* c) { return ens_grav_prep(c, pot); });
+    sg_status r = ens_grav_prep(e);
     return r != SG_OK ? r : ens_grav_launch(e, pot, e->st);
+}
+
+// Segmented update launches (all systems) with the contexts' bookkeeping.
+sg_status ens_launched(sg_ens* e, const char* what) {
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) return SG_OK;
+    char m[256];
+    snprintf(m, sizeof(m), "%s: %s", what, hipGetErrorString(err));
+    return e->fail(SG_EDEVICE, m);
+}
+
+// Neighbour lists and density of every system that lacks them: one launch
+// per stage for all systems when all lack them (every corrector), else
+// system by system.  beside: the launches share the GPU with the gravity
+// kernel (no LDS reservation in the gather passes).
+sg_status ens_lists_density(sg_ens* e, bool beside) {
+    sg_ctx* c0 = e->c[0];
+    bool all_nbr = true, all_rho = true, any = false;
+    for (sg_ctx* c : e->c) {
+        all_nbr = all_nbr && !c->have_nbr;
+        all_rho = all_rho && !c->have_rho;
+        any = any || !c->have_nbr || !c->have_rho;
+    }
+    if (!any) return SG_OK;
+    if (all_nbr && all_rho) {
+        c0->begin(SG_ST_SORT);
+        sg_seg_launch_sort(e->seg, e->st);
+        c0->end();
+        c0->begin(SG_ST_NBR);
+        sg_seg_launch_nbr_search(e->seg, e->st);
+        sg_seg_launch_scan_nbr(e->seg, e->st);
+        sg_seg_launch_nbr_finish(e->seg, e->st);
+        c0->end();
+        c0->begin(SG_ST_DENSITY);
+        sg_seg_launch_density(e->seg, beside ? 1 : 0, e->st);
+        c0->end();
+        for (sg_ctx* c : e->c) {
+            c->have_nbr = true;
+            c->have_rho = true;
+        }
+        return ens_launched(e, "neighbour lists and density");
+    }
+    sg_status r;
+    for (sg_ctx* c : e->c) {
+        c->beside_grav = beside;
+        r = !c->have_nbr ? do_build(c) : SG_OK;
+        if (r == SG_OK && !c->have_rho) r = do_density(c);
+        c->beside_grav = false;
+        if (r != SG_OK) return e->fail(r, c->msg);
+    }
+    return SG_OK;
 }
 
 sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
     if (flags & ~SG_POT) return e->fail(SG_EINVAL, "steps accept only SG_POT");
     if (!__builtin_isfinite(dt)) return e->fail(SG_EINVAL, "dt must be finite");
     const bool pot = (flags & SG_POT) != 0;
+    sg_ctx* c0 = e->c[0];
     sg_status r;
     bool need_grav = false;
+    // forces at r(t): lists and density are reused from the previous
+    // corrector, gravity likewise (the first step computes them)
     for (sg_ctx* c : e->c) {
         if (c->predicted) return e->fail(SG_ESTATE, "step inside a predict/correct pair");
-        if (!c->have_nbr && (r = do_build(c)) != SG_OK) return e->fail(r, c->msg);
-        if (!c->have_rho && (r = do_density(c)) != SG_OK) return e->fail(r, c->msg);
         need_grav |= !c->have_grav || (pot && !c->have_pot);
     }
+    if ((r = ens_lists_density(e, false)) != SG_OK) return r;
     if (need_grav && (r = ens_gravity(e, pot)) != SG_OK) return r;
-    // predictor, then each system's gravity inputs at the predicted positions
-    r = ens_each(e, [&](sg_ctx* c) {
-        sg_status q;
-        if ((q = do_sph(c)) != SG_OK) return q;
-        do_combine(c);
-        if ((q = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return q;
-        return ens_grav_prep(c, pot);
-    });
-    if (r != SG_OK) return r;
-    // the batched gravity on the shared stream beside every system's
-    // neighbour build, density and corrector SPH forces on the side streams
-    // (disjoint buffers; the gravity kernel reads only the prepared inputs),
-    // or before them with step_serial (of the first context)
-    auto chain = [&](sg_ctx* c) {
-        c->beside_grav = !e->c[0]->prm.step_serial;
-        sg_status q = do_build(c);
-        if (q == SG_OK) q = do_density(c);
-        if (q == SG_OK) q = do_sph(c);
-        c->beside_grav = false;
-        return q;
-    };
-    if (e->c[0]->prm.step_serial) {
-        if ((r = ens_grav_launch(e, pot, e->st)) != SG_OK) return r;
-        r = ens_each(e, chain);
-    } else if (!e->gst) {
-        r = ens_fork_join(e, [&] { return ens_grav_launch(e, pot, e->st); }, chain);
-    } else {
-        // gravity on its own stream and hardware queue, joined back only
-        // after every chain is enqueued: a hardware queue runs its packets
-        // in order, so neither the kernel nor a wait for it may sit ahead
-        // of a chain's launches in a queue that a side stream shares
-        bool forked = false;
-        auto launch = [&] {
-            if (hipEventRecord(e->gev[0], e->st) != hipSuccess ||
-                hipStreamWaitEvent(e->gst, e->gev[0], 0) != hipSuccess)
-                return e->fail(SG_EDEVICE, "fork to the gravity stream failed");
-            forked = true;
-            return ens_grav_launch(e, pot, e->gst);
-        };
-        r = ens_fork_join(e, launch, chain);
-        if (forked && (hipEventRecord(e->gev[1], e->gst) != hipSuccess ||
-                       hipStreamWaitEvent(e->st, e->gev[1], 0) != hipSuccess) && r == SG_OK)
-            r = e->fail(SG_EDEVICE, "join of the gravity stream failed");
+    // predictor: SPH right-hand side, total acceleration, update and the
+    // gravity inputs at the predicted positions, each one launch for all
+    c0->begin(SG_ST_SPH);
+    sg_seg_launch_sph_state(e->seg, 0, 0, e->st);
+    c0->end();
+    c0->begin(SG_ST_UPDATE);
+    sg_seg_launch_combine(e->seg, e->st);
+    sg_seg_launch_predict(e->seg, dt, e->st);
+    c0->end();
+    if ((r = ens_launched(e, "predictor")) != SG_OK) return r;
+    for (sg_ctx* c : e->c) {
+        c->invalidate_positions();
+        c->predicted = true;
+        c->accel_after_predict = false;
     }
-    if (r != SG_OK) return r;
-    return ens_each(e, [&](sg_ctx* c) {
-        do_combine(c);
+    if ((r = ens_grav_prep(e)) != SG_OK) return r;
+    // corrector right-hand side: the batched gravity beside every system's
+    // neighbour build, density and SPH forces (disjoint buffers; the
+    // gravity kernel reads only the prepared inputs), or before them with
+    // step_serial (of the first context)
+    auto chains = [&]() {
+        const bool beside = !c0->prm.step_serial && e->gst;
+        sg_status q = ens_lists_density(e, beside);
+        if (q != SG_OK) return q;
+        c0->begin(SG_ST_SPH);
+        sg_seg_launch_sph_state(e->seg, 1, beside ? 1 : 0, e->st);
+        c0->end();
+        for (sg_ctx* c : e->c) c->have_sph = true;
+        return ens_launched(e, "SPH forces");
+    };
+    if (c0->prm.step_serial || !e->gst) {
+        if ((r = ens_grav_launch(e, pot, e->st)) != SG_OK) return r;
+        if ((r = chains()) != SG_OK) return r;
+    } else {
+        if (hipEventRecord(e->gev[0], e->st) != hipSuccess ||
+            hipStreamWaitEvent(e->gst, e->gev[0], 0) != hipSuccess)
+            return e->fail(SG_EDEVICE, "fork to the gravity stream failed");
+        r = ens_grav_launch(e, pot, e->gst);
+        sg_status rc = r == SG_OK ? chains() : r;
+        // join (also after an error, so that a capture stays whole)
+        if ((hipEventRecord(e->gev[1], e->gst) != hipSuccess ||
+             hipStreamWaitEvent(e->st, e->gev[1], 0) != hipSuccess) && rc == SG_OK)
+            rc = e->fail(SG_EDEVICE, "join of the gravity stream failed");
+        if (rc != SG_OK) return rc;
+    }
+    // corrector update, one launch each for all systems
+    c0->begin(SG_ST_UPDATE);
+    sg_seg_launch_combine(e->seg, e->st);
+    sg_seg_launch_correct(e->seg, dt, e->st);
+    c0->end();
+    for (sg_ctx* c : e->c) {
         c->accel_after_predict = true;
-        return do_kick_drift(c, dt, SG_CORRECT);
-    });
+        c->predicted = false;
+        c->have_sph = false;       // the SPH part was evaluated with the predicted velocities
+    }
+    return ens_launched(e, "corrector");
 }
 
 }  // namespace
@@ -1212,23 +1245,21 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
 
 size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles) {
     if (nsys < 1 || total_particles < 1) return 0;
-    size_t a, b;
-    return ens_layout(nsys, total_particles / 64 + nsys, &a, &b);
+    return ens_layout(nsys, total_particles / 64 + nsys).total;
 }
 
 sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size_t ws_bytes,
-                             void* const* side_streams, int32_t nside, void* grav_stream,
-                             sg_ens** out) {
+                             void* grav_stream, sg_ens** out) {
     if (!out || !ctxs || nsys < 1) return SG_EINVAL;
     *out = nullptr;
     if (!d_ws || ((uintptr_t)d_ws & (kAlign - 1))) return SG_EINVAL;
-    if (nside < 0 || nside > 64 || (nside > 0 && !side_streams)) return SG_EINVAL;
+    if (!ctxs[0] || !ctxs[0]->bound) return SG_EINVAL;
+    if (grav_stream && grav_stream == (void*)ctxs[0]->st) return SG_EINVAL;
     std::vector<sg_ens_sys> sys((size_t)nsys);
+    std::vector<sg_seg_sys> seg((size_t)nsys);
+    std::vector<int64_t> pfx((size_t)SG_SEG_NPFX * (nsys + 1), 0);
     std::vector<std::pair<int64_t, sg_ens_task>> tasks;
     int64_t total = 0;
-    if (!ctxs[0] || !ctxs[0]->bound) return SG_EINVAL;
-    for (int32_t i = 0; i < nside; ++i)
-        if (!side_streams[i] || side_streams[i] == (void*)ctxs[0]->st) return SG_EINVAL;
     // launch shape of the first context: 256 * ipl targets per task.  Unset
     // fields take the batched launch's measured best at 64 systems of
     // 8192-262144 particles, 2 targets per lane and 512 sources per tile
@@ -1244,6 +1275,8 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
         if (c->st != ctxs[0]->st || c->prm.G != ctxs[0]->prm.G || c->prm.eps != ctxs[0]->prm.eps ||
             c->prm.grav_reorder != ctxs[0]->prm.grav_reorder)
             return SG_EINVAL;
+        for (int32_t j = 0; j < k; ++j)
+            if (ctxs[j] == c) return SG_EINVAL;      // each system once
         sg_ens_sys& S = sys[(size_t)k];
         sg_grav_sorted_ptrs(c->at<void>(c->L.gsorted), c->n, &S.xs, &S.ys, &S.zs, &S.ms, &S.sbox);
         S.order = c->at<int32_t>(c->L.gorder);
@@ -1255,14 +1288,78 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
         const int64_t nb = (c->n + per - 1) / per;
         for (int64_t b = 0; b < nb; ++b) tasks.push_back({c->n, sg_ens_task{k, (int32_t)b}});
         total += c->n;
+        // the segmented launches' view of the same system
+        sg_seg_sys& Q = seg[(size_t)k];
+        Q.x = c->s.x;
+        Q.y = c->s.y;
+        Q.z = c->s.z;
+        Q.vx = c->s.vx;
+        Q.vy = c->s.vy;
+        Q.vz = c->s.vz;
+        Q.m = c->s.m;
+        Q.e = c->s.e;
+        Q.ax = c->s.ax;
+        Q.ay = c->s.ay;
+        Q.az = c->s.az;
+        Q.dedt = c->s.dedt;
+        Q.rho = c->s.rho;
+        Q.h = c->s.h;
+        Q.key = c->at<int32_t>(c->L.key);
+        Q.count = c->at<int32_t>(c->L.count);
+        Q.cursor = c->at<int32_t>(c->L.cursor);
+        Q.tmp = c->at<int32_t>(c->L.tmp);
+        Q.ncnt = c->at<int32_t>(c->L.ncnt);
+        Q.slots = c->at<int32_t>(c->L.nbr_slots);
+        Q.hmax = c->at<unsigned long long>(c->L.hmax);
+        Q.off = c->at<int64_t>(c->L.off);
+        Q.scan = c->at<void>(c->L.scan);
+        Q.cell_cap = c->caps.cell_cap;
+        Q.nnz_cap = c->caps.nnz_cap;
+        Q.cell_scale = c->prm.cell_scale_log2 < 0 ? 0.5 : (c->prm.cell_scale_log2 > 0 ? 2.0 : 1.0);
+        Q.vtx = c->at<double>(c->L.vtx);
+        Q.vty = c->at<double>(c->L.vty);
+        Q.vtz = c->at<double>(c->L.vtz);
+        Q.et = c->at<double>(c->L.et);
+        Q.asx = c->at<double>(c->L.asx);
+        Q.asy = c->at<double>(c->L.asy);
+        Q.asz = c->at<double>(c->L.asz);
+        Q.gx = S.gx;
+        Q.gy = S.gy;
+        Q.gz = S.gz;
+        Q.sph = c->sph();
+        Q.sph.beside_grav = 0;
+        Q.g = c->grid();
+        sg_morton_ptrs(c->at<void>(c->L.morton), c->n, &Q.mk0, &Q.mk1, &Q.mv0, &Q.mv1, &Q.mhist,
+                       &Q.moffs, &Q.ntiles);
+        Q.order = c->at<int32_t>(c->L.gorder);
+        Q.xs = const_cast<double*>(S.xs);
+        Q.ys = const_cast<double*>(S.ys);
+        Q.zs = const_cast<double*>(S.zs);
+        Q.ms = const_cast<double*>(S.ms);
+        Q.sbox = const_cast<void*>(S.sbox);
+        Q.n = c->n;
+        Q.ng = c->ng;
+        Q.gamma = c->prm.gamma;
+        Q.alpha = c->prm.alpha;
+        Q.beta = c->prm.beta;
+        Q.eta = c->prm.eta;
+        const bool gas = c->ng > 0;
+        const int64_t cnt[SG_SEG_NPFX] = {(c->n + 255) / 256,
+                                          (c->ng + 255) / 256,
+                                          Q.ntiles,
+                                          gas ? sg_cells_clear_blocks(c->caps.cell_cap) : 0,
+                                          gas ? sg_scan_tiles(c->caps.cell_cap) : 0,
+                                          gas ? sg_scan_tiles(c->ng) : 0,
+                                          (c->ng + 3) / 4};
+        for (int q = 0; q < SG_SEG_NPFX; ++q)
+            pfx[(size_t)q * (nsys + 1) + k + 1] = pfx[(size_t)q * (nsys + 1) + k] + cnt[q];
     }
     // largest systems first (their tasks are the longest)
     std::stable_sort(tasks.begin(), tasks.end(),
                      [](const std::pair<int64_t, sg_ens_task>& a,
                         const std::pair<int64_t, sg_ens_task>& b) { return a.first > b.first; });
-    size_t o_tasks, o_counter;
-    const size_t need = ens_layout(nsys, (int64_t)tasks.size(), &o_tasks, &o_counter);
-    if (ws_bytes < need || (int64_t)tasks.size() > total / 64 + nsys) return SG_EINVAL;
+    const ens_offsets o = ens_layout(nsys, (int64_t)tasks.size());
+    if (ws_bytes < o.total || (int64_t)tasks.size() > total / 64 + nsys) return SG_EINVAL;
     std::vector<sg_ens_task> tk(tasks.size());
     for (size_t i = 0; i < tasks.size(); ++i) tk[i] = tasks[i].second;
     sg_ens* e = new (std::nothrow) sg_ens();
@@ -1271,56 +1368,43 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
     e->st = ctxs[0]->st;
     char* ws = (char*)d_ws;
     e->d_sys = (sg_ens_sys*)ws;
-    e->d_tasks = (sg_ens_task*)(ws + o_tasks);
-    e->d_counter = (int32_t*)(ws + o_counter);
+    e->d_tasks = (sg_ens_task*)(ws + o.tasks);
+    e->d_counter = (int32_t*)(ws + o.counter);
     e->ntasks = (int32_t)tk.size();
     e->ipl = ipl;
     e->tile = tile;
     e->eps = ctxs[0]->prm.eps;
     e->G = ctxs[0]->prm.G;
+    e->seg.sys = (const sg_seg_sys*)(ws + o.seg);
+    e->seg.pfx = (const int64_t*)(ws + o.pfx);
+    e->seg.nsys = nsys;
+    for (int q = 0; q < SG_SEG_NPFX; ++q) e->seg.nblk[q] = pfx[(size_t)q * (nsys + 1) + nsys];
     e->msg[0] = 0;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // the caller's side streams for the systems' own launches (at most
-    // one per system is used)
-    const int use_side = nside < nsys ? nside : nsys;
-    for (int i = 0; i < use_side; ++i) e->side.push_back((hipStream_t)side_streams[i]);
-    for (size_t i = 0; i < e->side.size() + 1 && !e->side.empty(); ++i) {
-        hipEvent_t x = nullptr;
-        if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) break;
-        e->ev.push_back(x);
-    }
-    if (e->ev.size() != e->side.size() + 1) {          // fall back to the shared stream
-        for (hipEvent_t x : e->ev) (void)hipEventDestroy(x);
-        e->side.clear();
-        e->ev.clear();
-    }
-    if (!e->side.empty()) {
-        // the gravity stream: the caller's, else one with every CU in its
-        // mask.  A stream of the runtime's default kind shares one of the
-        // process's few hardware queues with other streams, and a queue
-        // runs its packets in order, so a chain enqueued behind the
-        // persistent gravity kernel in a shared queue would wait for it;
-        // a CU-masked stream gets a hardware queue of its own.
-        e->own_gst = grav_stream == nullptr;
-        if (grav_stream) {
-            e->gst = (hipStream_t)grav_stream;
-        } else {
-            std::vector<uint32_t> mask((size_t)((cus > 0 ? cus : 256) + 31) / 32, 0xffffffffu);
-            if (cus > 0 && cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
-            if (hipExtStreamCreateWithCUMask(&e->gst, (uint32_t)mask.size(), mask.data()) != hipSuccess)
-                e->gst = nullptr;
-        }
-        if (!e->gst ||
-            hipEventCreateWithFlags(&e->gev[0], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&e->gev[1], hipEventDisableTiming) != hipSuccess) {
-            if (e->gst && e->own_gst) (void)hipStreamDestroy(e->gst);   // fall back: gravity on st
+    // the gravity stream: the caller's, else one with every CU in its mask.
+    // A stream of the runtime's default kind shares one of the process's
+    // few hardware queues with other streams, and a queue runs its packets
+    // in order, so the systems' launches enqueued behind the persistent
+    // gravity kernel in a shared queue would wait for it; a CU-masked
+    // stream gets a hardware queue of its own.
+    e->own_gst = grav_stream == nullptr;
+    if (grav_stream) {
+        e->gst = (hipStream_t)grav_stream;
+    } else {
+        std::vector<uint32_t> mask((size_t)((cus > 0 ? cus : 256) + 31) / 32, 0xffffffffu);
+        if (cus > 0 && cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
+        if (hipExtStreamCreateWithCUMask(&e->gst, (uint32_t)mask.size(), mask.data()) != hipSuccess)
             e->gst = nullptr;
-            for (hipEvent_t& x : e->gev) {
-                if (x) (void)hipEventDestroy(x);
-                x = nullptr;
-            }
+    }
+    if (!e->gst || hipEventCreateWithFlags(&e->gev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e->gev[1], hipEventDisableTiming) != hipSuccess) {
+        if (e->gst && e->own_gst) (void)hipStreamDestroy(e->gst);   // fall back: gravity on st
+        e->gst = nullptr;
+        for (hipEvent_t& x : e->gev) {
+            if (x) (void)hipEventDestroy(x);
+            x = nullptr;
         }
     }
     // persistent grid: as many workgroups as are resident at once
@@ -1332,6 +1416,10 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
                        e->st) != hipSuccess ||
         hipMemcpyAsync(e->d_tasks, tk.data(), sizeof(sg_ens_task) * tk.size(),
                        hipMemcpyHostToDevice, e->st) != hipSuccess ||
+        hipMemcpyAsync(ws + o.seg, seg.data(), sizeof(sg_seg_sys) * seg.size(),
+                       hipMemcpyHostToDevice, e->st) != hipSuccess ||
+        hipMemcpyAsync(ws + o.pfx, pfx.data(), sizeof(int64_t) * pfx.size(), hipMemcpyHostToDevice,
+                       e->st) != hipSuccess ||
         hipStreamSynchronize(e->st) != hipSuccess) {
         delete e;
         return SG_EDEVICE;
@@ -1344,10 +1432,12 @@ sg_status sg_ensemble_gravity(sg_ens* e, uint32_t flags) {
     if (!e) return SG_EINVAL;
     if (flags & ~(SG_GRAV | SG_POT)) return e->fail(SG_EINVAL, "flags: SG_GRAV [| SG_POT]");
     (void)hipGetLastError();
+    for (sg_ctx* c : e->c)
+        if (c->predicted) return e->fail(SG_ESTATE, "gravity inside a predict/correct pair");
     sg_status r = ens_gravity(e, (flags & SG_POT) != 0);
     if (r != SG_OK) return r;
     for (sg_ctx* c : e->c) do_combine(c);
-    return SG_OK;
+    return ens_launched(e, "combine");
 }
 
 sg_status sg_ensemble_step(sg_ens* e, double dt, uint32_t flags) {

@@ -590,13 +590,13 @@ __global__ void k_counter_reset(int32_t* counter) {
 }
 
 // Gather positions and masses into Morton order and build the bounding box
-// of every run of kSub sorted particles (one wavefront per run).
-__global__ __launch_bounds__(kBlock) void k_sorted_boxes(
+// of every run of kSub sorted particles (one wavefront per run): sorted
+// index i of a launch whose blocks cover [0, n) in 256s.
+__device__ inline void sorted_boxes_one(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ m, const int32_t* __restrict__ order, int64_t n,
+    const double* __restrict__ m, const int32_t* __restrict__ order, int64_t n, int64_t i,
     double* __restrict__ xs, double* __restrict__ ys, double* __restrict__ zs,
     double* __restrict__ ms, box6* __restrict__ sbox, uint32_t* __restrict__ err) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool v = i < n;
     double p[3] = {0, 0, 0};
     if (v) {
@@ -627,6 +627,25 @@ __global__ __launch_bounds__(kBlock) void k_sorted_boxes(
     }
     const int64_t q = i / kSub;
     if ((threadIdx.x & 63) == 0 && q * kSub < n) sbox[q] = b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sorted_boxes(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ m, const int32_t* __restrict__ order, int64_t n,
+    double* __restrict__ xs, double* __restrict__ ys, double* __restrict__ zs,
+    double* __restrict__ ms, box6* __restrict__ sbox, uint32_t* __restrict__ err) {
+    sorted_boxes_one(x, y, z, m, order, n, (int64_t)blockIdx.x * kBlock + threadIdx.x, xs, ys, zs,
+                     ms, sbox, err);
+}
+
+// The same for every system of an ensemble (blocks of 256 particles).
+__global__ __launch_bounds__(kBlock) void k_seg_sorted_boxes(const sg_seg_sys* __restrict__ sys,
+                                                             const int64_t* __restrict__ pfx,
+                                                             int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    sorted_boxes_one(S.x, S.y, S.z, S.m, S.order, S.n, lb * kBlock + threadIdx.x, S.xs, S.ys,
+                     S.zs, S.ms, (box6*)S.sbox, &S.g->err);
 }
 
 __global__ __launch_bounds__(kBlock) void k_grav_reduce(const double* __restrict__ part,
@@ -800,6 +819,12 @@ int sg_launch_grav_sorted(const sg_grav_args& a_in, hipStream_t st) {
                        a.n, (double*)a.xs, (double*)a.ys, (double*)a.zs, (double*)a.ms,
                        (box6*)a.sbox, a.err);
     return 0;
+}
+
+void sg_seg_launch_grav_sorted(const sg_seg& s, hipStream_t st) {
+    if (s.nblk[SG_SEG_N] > 0)
+        hipLaunchKernelGGL(k_seg_sorted_boxes, dim3((unsigned)s.nblk[SG_SEG_N]), dim3(kBlock), 0,
+                           st, s.sys, s.pfx + SG_SEG_N * (s.nsys + 1), s.nsys);
 }
 
 int sg_launch_gravity(const sg_grav_args& a_in, hipStream_t st) {

@@ -37,6 +37,21 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// System of block b of a segmented launch: the largest s with p[s] <= b
+// (p = per-system prefix of block counts, p[0] = 0; systems without blocks
+// are never found); *local = b - p[s].
+__device__ inline int sg_seg_find(const int64_t* __restrict__ p, int nsys, int64_t b,
+                                  int64_t* local) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    *local = b - p[lo];
+    return lo;
+}
+
 struct sg_grid_dev {
     // reduction inputs (order-preserving u64 images of doubles)
     unsigned long long hmin_bits;
@@ -205,6 +220,81 @@ int sg_grav_ensemble_blocks_per_cu(int ipl, int tile, int with_pot);
 size_t sg_morton_tmp_bytes(int64_t n);
 void sg_launch_morton_order(const double* x, const double* y, const double* z, int64_t n,
                             sg_grid_dev* g, int32_t* order, void* tmp, hipStream_t st);
+
+// Segmented launches: one launch covers a stage for every system of an
+// ensemble.  Each system's pointers sit in a device table; a launch's
+// blocks are dealt to systems by a prefix of per-system block counts (the
+// block of a system is found by a search over that prefix, uniform per
+// workgroup).  Each kernel body is the one of the per-system kernel, so
+// results are the same bit for bit.
+struct sg_seg_sys {
+    // caller's state
+    double *x, *y, *z, *vx, *vy, *vz, *m, *e, *ax, *ay, *az, *dedt, *rho;
+    // workspace: predictor values, SPH and gravity parts
+    double *vtx, *vty, *vtz, *et;
+    double *asx, *asy, *asz;
+    double *gx, *gy, *gz;
+    sg_sph_bufs sph;
+    sg_grid_dev* g;
+    // Morton order: key/value ping-pong buffers, digit histograms and
+    // their offsets, the order, sorted copies and 64-particle boxes
+    uint32_t *mk0, *mk1;
+    int32_t *mv0, *mv1;
+    int32_t* mhist;
+    int64_t* moffs;
+    int32_t* order;
+    double *xs, *ys, *zs, *ms;
+    void* sbox;
+    // gas sort and neighbour lists
+    double* h;                       // caller's smoothing lengths
+    int32_t *key, *count, *cursor, *tmp, *ncnt, *slots;
+    unsigned long long* hmax;
+    int64_t* off;
+    void* scan;                      // scan scratch (block sums)
+    int64_t n, ng, ntiles, cell_cap, nnz_cap;
+    double cell_scale;
+    double gamma, alpha, beta, eta;
+};
+// Block prefixes of a segmented launch, per system: blocks of 256
+// particles, of 256 gas particles, radix tiles, cell-clearing blocks
+// (grid-stride, at most 256 per system), scan tiles of the cell counts and
+// of the neighbour counts, and blocks of 4 gas particles (one wavefront
+// each).
+enum {
+    SG_SEG_N = 0, SG_SEG_NG = 1, SG_SEG_TILES = 2, SG_SEG_CELLS = 3, SG_SEG_SCAN_C = 4,
+    SG_SEG_SCAN_G = 5, SG_SEG_NG4 = 6, SG_SEG_NPFX = 7
+};
+struct sg_seg {
+    const sg_seg_sys* sys;           // [nsys], device
+    const int64_t* pfx;              // [SG_SEG_NPFX][nsys + 1] block prefixes, device
+    int32_t nsys;
+    int64_t nblk[SG_SEG_NPFX];       // totals of the prefixes (host)
+};
+// Host helpers for building the table.
+void sg_morton_ptrs(void* tmp, int64_t n, uint32_t** k0, uint32_t** k1, int32_t** v0,
+                    int32_t** v1, int32_t** hist, int64_t** offs, int64_t* ntiles);
+int64_t sg_radix_tiles(int64_t n);
+int64_t sg_scan_tiles(int64_t cap);          // blocks of one sg_launch_scan pass
+int64_t sg_cells_clear_blocks(int64_t cell_cap);
+// Stages (each one launch, or a few, for all systems).
+
+void sg_seg_launch_combine(const sg_seg& s, hipStream_t st);
+void sg_seg_launch_predict(const sg_seg& s, double dt, hipStream_t st);
+void sg_seg_launch_correct(const sg_seg& s, double dt, hipStream_t st);
+void sg_seg_launch_morton_order(const sg_seg& s, hipStream_t st);
+void sg_seg_launch_grav_sorted(const sg_seg& s, hipStream_t st);
+// The neighbour build of every system, in the order of the per-system
+// launches: the gas sort (grid rule, keys and counts, cell offsets, stable
+// reorder and gather), the search, the scan of the neighbour counts into
+// CSR offsets, the capacity check and the copy into the CSR rows.
+void sg_seg_launch_sort(const sg_seg& s, hipStream_t st);
+void sg_seg_launch_nbr_search(const sg_seg& s, hipStream_t st);
+void sg_seg_launch_scan_nbr(const sg_seg& s, hipStream_t st);
+void sg_seg_launch_nbr_finish(const sg_seg& s, hipStream_t st);
+// Density, and the EOS records + FP32C forces on the predicted state
+// (predicted != 0: vt, et) or the current one; `beside_grav` as in sg_sph_bufs.
+void sg_seg_launch_density(const sg_seg& s, int beside_grav, hipStream_t st);
+void sg_seg_launch_sph_state(const sg_seg& s, int predicted, int beside_grav, hipStream_t st);
 
 // Update and diagnostics.
 void sg_launch_predict(int64_t n, int64_t ng, double dt, double* x, double* y, double* z,

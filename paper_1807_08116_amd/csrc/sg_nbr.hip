@@ -172,16 +172,15 @@ __device__ inline float lane_f32(float v, int L) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), L));
 }
 
-__global__ __launch_bounds__(kBlock) void k_nbr_search(
+// The search of wavefront w (target slots 64 w .. 64 w + 63); w is uniform.
+__device__ __attribute__((always_inline)) inline void nbr_search_wave(
     const sg_grid_dev* __restrict__ g, int64_t ng, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ hs,
     const int64_t* __restrict__ off, const int32_t* __restrict__ perm,
-    const int32_t* __restrict__ key, int32_t* __restrict__ cnt, int32_t* __restrict__ slots) {
+    const int32_t* __restrict__ key, int32_t* __restrict__ cnt, int32_t* __restrict__ slots,
+    int32_t w) {
     if (g->err & SGE_SORT_FATAL) return;
     const unsigned lane = threadIdx.x & 63;
-    // first target slot of this wavefront (uniform: held in a scalar register)
-    const int32_t w = __builtin_amdgcn_readfirstlane(
-        (int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
     const int64_t g0 = (int64_t)w * 64;
     if (g0 >= ng) return;
     const int64_t s = g0 + lane;
@@ -293,17 +292,28 @@ __global__ __launch_bounds__(kBlock) void k_nbr_search(
     if (live) cnt[s] = mine;
 }
 
+__global__ __launch_bounds__(kBlock) void k_nbr_search(
+    const sg_grid_dev* __restrict__ g, int64_t ng, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ hs,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ key, int32_t* __restrict__ cnt, int32_t* __restrict__ slots) {
+    // first target slot of this wavefront (uniform: held in a scalar register)
+    const int32_t w = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
+    nbr_search_wave(g, ng, xs, ys, zs, hs, off, perm, key, cnt, slots, w);
+}
+
 // Move every target's slot to its CSR row (or search again into the row
 // when the slot was too short).
-__global__ __launch_bounds__(kBlock) void k_nbr_compact(
+// Target s (uniform across the wavefront).
+__device__ __attribute__((always_inline)) inline void nbr_compact_wave(
     const sg_grid_dev* __restrict__ g, int64_t ng, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ hs,
     const int64_t* __restrict__ off, const int32_t* __restrict__ cnt,
     const int32_t* __restrict__ slots, const int64_t* __restrict__ nbr_off,
-    int32_t* __restrict__ nbr_idx) {
+    int32_t* __restrict__ nbr_idx, int64_t s) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
     const unsigned lane = threadIdx.x & 63;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (s >= ng) return;
     const int64_t c = cnt[s], to = nbr_off[s];
     if (c <= kSlot) {
@@ -318,9 +328,18 @@ __global__ __launch_bounds__(kBlock) void k_nbr_compact(
     });
 }
 
-__global__ void k_nbr_check(sg_grid_dev* g, const int64_t* __restrict__ nbr_off, int64_t ng,
-                            int64_t nnz_cap) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(kBlock) void k_nbr_compact(
+    const sg_grid_dev* __restrict__ g, int64_t ng, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ hs,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ cnt,
+    const int32_t* __restrict__ slots, const int64_t* __restrict__ nbr_off,
+    int32_t* __restrict__ nbr_idx) {
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+    nbr_compact_wave(g, ng, xs, ys, zs, hs, off, cnt, slots, nbr_off, nbr_idx, s);
+}
+
+__device__ inline void nbr_check_one(sg_grid_dev* g, const int64_t* __restrict__ nbr_off,
+                                     int64_t ng, int64_t nnz_cap) {
     if (g->err & SGE_SORT_FATAL) return;
     const int64_t nnz = nbr_off[ng];
     g->nnz = nnz;
@@ -330,12 +349,59 @@ __global__ void k_nbr_check(sg_grid_dev* g, const int64_t* __restrict__ nbr_off,
     }
 }
 
+__global__ void k_nbr_check(sg_grid_dev* g, const int64_t* __restrict__ nbr_off, int64_t ng,
+                            int64_t nnz_cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    nbr_check_one(g, nbr_off, ng, nnz_cap);
+}
+
+// ----------------------------------------------------- all systems at once --
+// (see sg_seg in sg_internal.h)
+
+__global__ __launch_bounds__(kBlock) void k_seg_nbr_search(const sg_seg_sys* __restrict__ sys,
+                                                           const int64_t* __restrict__ pfx,
+                                                           int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    const int32_t w = __builtin_amdgcn_readfirstlane((int32_t)(lb * kWaves + (threadIdx.x >> 6)));
+    const sg_sph_bufs& b = S.sph;
+    nbr_search_wave(S.g, S.ng, b.xs, b.ys, b.zs, b.hs, S.off, b.perm, S.key, S.ncnt, S.slots, w);
+}
+
+__global__ void k_seg_nbr_check(const sg_seg_sys* __restrict__ sys, int nsys) {
+    for (int k = threadIdx.x; k < nsys; k += blockDim.x)
+        if (sys[k].ng > 0) nbr_check_one(sys[k].g, sys[k].sph.nbr_off, sys[k].ng, sys[k].nnz_cap);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_nbr_compact(const sg_seg_sys* __restrict__ sys,
+                                                            const int64_t* __restrict__ pfx,
+                                                            int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    const sg_sph_bufs& b = S.sph;
+    nbr_compact_wave(S.g, S.ng, b.xs, b.ys, b.zs, b.hs, S.off, S.ncnt, S.slots, b.nbr_off,
+                     const_cast<int32_t*>(b.nbr_idx), lb * kWaves + (threadIdx.x >> 6));
+}
+
 inline unsigned waves_grid(int64_t n) {
     int64_t b = (n + kWaves - 1) / kWaves;
     return (unsigned)(b < 1 ? 1 : b);
 }
 
 }  // namespace
+
+void sg_seg_launch_nbr_search(const sg_seg& s, hipStream_t st) {
+    if (s.nblk[SG_SEG_NG] > 0)
+        hipLaunchKernelGGL(k_seg_nbr_search, dim3((unsigned)s.nblk[SG_SEG_NG]), dim3(kBlock), 0, st,
+                           s.sys, s.pfx + SG_SEG_NG * (s.nsys + 1), s.nsys);
+}
+
+void sg_seg_launch_nbr_finish(const sg_seg& s, hipStream_t st) {
+    if (s.nblk[SG_SEG_NG4] == 0) return;
+    hipLaunchKernelGGL(k_seg_nbr_check, dim3(1), dim3(64), 0, st, s.sys, s.nsys);
+    hipLaunchKernelGGL(k_seg_nbr_compact, dim3((unsigned)s.nblk[SG_SEG_NG4]), dim3(kBlock), 0, st,
+                       s.sys, s.pfx + SG_SEG_NG4 * (s.nsys + 1), s.nsys);
+}
 
 size_t sg_nbr_slot_bytes(int64_t ng) { return 4 * (size_t)kSlot * (size_t)(ng > 0 ? ng : 0); }
 

@@ -47,13 +47,9 @@ __device__ inline int64_t scan_n(int64_t n_host, const int64_t* n_dev, int64_t c
     return n < cap ? n : cap;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t* __restrict__ in,
-                                                        int64_t n_host,
-                                                        const int64_t* __restrict__ n_dev,
-                                                        int64_t cap,
-                                                        int64_t* __restrict__ bsum) {
-    const int64_t n = scan_n(n_host, n_dev, cap);
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+__device__ inline void scan_reduce_tile(const int32_t* __restrict__ in, int64_t n, int64_t tile,
+                                        int64_t* __restrict__ bsum) {
+    const int64_t base = tile * kScanTile;
     int64_t s = 0;
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + k * kBlock + threadIdx.x;
@@ -66,17 +62,23 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t* __restric
     if (threadIdx.x == 0) {
         int64_t t = 0;
         for (int w = 0; w < kBlock / 64; ++w) t += ws[w];
-        bsum[blockIdx.x] = t;
+        bsum[tile] = t;
     }
 }
 
-// Single block: exclusive scan of the block sums in place; out[n] = total.
-// 256 threads, 4 sums each per pass: one wavefront per SIMD, so the block
-// also finds room on CUs that another kernel's workgroups mostly fill.
-__global__ __launch_bounds__(256) void k_scan_bsums(int64_t* __restrict__ bsum, int64_t n_host,
-                                                    const int64_t* __restrict__ n_dev,
-                                                    int64_t cap, int64_t* __restrict__ out) {
-    const int64_t n = scan_n(n_host, n_dev, cap);
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t* __restrict__ in,
+                                                        int64_t n_host,
+                                                        const int64_t* __restrict__ n_dev,
+                                                        int64_t cap,
+                                                        int64_t* __restrict__ bsum) {
+    scan_reduce_tile(in, scan_n(n_host, n_dev, cap), blockIdx.x, bsum);
+}
+
+// Exclusive scan of the block sums in place; out[n] = total.  256 threads,
+// 4 sums each per pass: one wavefront per SIMD, so the block also finds
+// room on CUs that another kernel's workgroups mostly fill.
+__device__ inline void scan_bsums_block(int64_t* __restrict__ bsum, int64_t n,
+                                        int64_t* __restrict__ out) {
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     __shared__ int64_t buf[256];
     __shared__ int64_t carry;
@@ -110,13 +112,16 @@ __global__ __launch_bounds__(256) void k_scan_bsums(int64_t* __restrict__ bsum, 
     if (threadIdx.x == 0) out[n] = carry;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t* __restrict__ in,
-                                                      int64_t* __restrict__ out, int64_t n_host,
-                                                      const int64_t* __restrict__ n_dev,
-                                                      int64_t cap,
-                                                      const int64_t* __restrict__ bsum) {
-    const int64_t n = scan_n(n_host, n_dev, cap);
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+__global__ __launch_bounds__(256) void k_scan_bsums(int64_t* __restrict__ bsum, int64_t n_host,
+                                                    const int64_t* __restrict__ n_dev,
+                                                    int64_t cap, int64_t* __restrict__ out) {
+    scan_bsums_block(bsum, scan_n(n_host, n_dev, cap), out);
+}
+
+__device__ inline void scan_down_tile(const int32_t* __restrict__ in, int64_t* __restrict__ out,
+                                      int64_t n, int64_t tile,
+                                      const int64_t* __restrict__ bsum) {
+    const int64_t base = tile * kScanTile;
     if (base >= n) return;
     const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
     int64_t v[kScanItems];
@@ -136,11 +141,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t* __restrict_
     __syncthreads();
     int64_t wbase = 0;
     for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += wtot[w];
-    int64_t run = bsum[blockIdx.x] + wbase + incl - tsum;
+    int64_t run = bsum[tile] + wbase + incl - tsum;
     for (int k = 0; k < kScanItems; ++k) {
         if (i0 + k < n) out[i0 + k] = run;
         run += v[k];
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t* __restrict__ in,
+                                                      int64_t* __restrict__ out, int64_t n_host,
+                                                      const int64_t* __restrict__ n_dev,
+                                                      int64_t cap,
+                                                      const int64_t* __restrict__ bsum) {
+    scan_down_tile(in, out, scan_n(n_host, n_dev, cap), blockIdx.x, bsum);
 }
 
 // ------------------------------------------------------------ grid rule --
@@ -176,7 +189,7 @@ __global__ void k_status_clear(sg_grid_dev* g) {
     }
 }
 
-__global__ void k_grid_reset(sg_grid_dev* g) {
+__device__ inline void grid_reset_one(sg_grid_dev* g) {
     int t = threadIdx.x;
     if (t == 0) {
         g->hmin_bits = ~0ull;
@@ -196,25 +209,23 @@ __global__ void k_grid_reset(sg_grid_dev* g) {
     // glo / ghi belong to the gravity preparation, which resets them itself
 }
 
-// Minimum h and validity of the gas state.
-__global__ __launch_bounds__(kBlock) void k_grid_hmin(const double* __restrict__ x,
-                                                      const double* __restrict__ y,
-                                                      const double* __restrict__ z,
-                                                      const double* __restrict__ h, int64_t ng,
-                                                      sg_grid_dev* g) {
-    unsigned long long mn = ~0ull;
-    bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ng;
-         i += (int64_t)gridDim.x * kBlock) {
-        double hi = h[i];
-        if (!(hi > 0.0) || !finite_d(hi) || !finite_d(x[i]) || !finite_d(y[i]) || !finite_d(z[i]))
-            bad = true;
-        else {
-            unsigned long long o = sg_ord(hi);
-            mn = o < mn ? o : mn;
-        }
+__global__ void k_grid_reset(sg_grid_dev* g) { grid_reset_one(g); }
+
+// Minimum h and validity of the gas state: a thread's items, then the
+// wavefront and workgroup minimum, one global atomic per workgroup.
+__device__ inline void hmin_item(const double* __restrict__ x, const double* __restrict__ y,
+                                 const double* __restrict__ z, const double* __restrict__ h,
+                                 int64_t i, unsigned long long& mn, bool& bad) {
+    double hi = h[i];
+    if (!(hi > 0.0) || !finite_d(hi) || !finite_d(x[i]) || !finite_d(y[i]) || !finite_d(z[i]))
+        bad = true;
+    else {
+        unsigned long long o = sg_ord(hi);
+        mn = o < mn ? o : mn;
     }
-    // wavefront, then workgroup minimum: one global atomic per workgroup
+}
+
+__device__ inline void hmin_fold(unsigned long long mn, bool bad, sg_grid_dev* g) {
     __shared__ unsigned long long s_mn[kBlock / 64];
     mn = wave_min_u64(mn);
     if (lane_id() == 0) s_mn[threadIdx.x >> 6] = mn;
@@ -226,12 +237,27 @@ __global__ __launch_bounds__(kBlock) void k_grid_hmin(const double* __restrict__
     if (bad) atomicOr(&g->err, SGE_NONFINITE);
 }
 
+__global__ __launch_bounds__(kBlock) void k_grid_hmin(const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ z,
+                                                      const double* __restrict__ h, int64_t ng,
+                                                      sg_grid_dev* g) {
+    unsigned long long mn = ~0ull;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ng;
+         i += (int64_t)gridDim.x * kBlock)
+        hmin_item(x, y, z, h, i, mn, bad);
+    hmin_fold(mn, bad, g);
+}
+
 // Per-level bounding boxes, maximum h and particle counts.
-__global__ __launch_bounds__(kBlock) void k_grid_levels(const double* __restrict__ x,
-                                                        const double* __restrict__ y,
-                                                        const double* __restrict__ z,
-                                                        const double* __restrict__ h,
-                                                        int64_t ng, sg_grid_dev* g) {
+// Items base + r * stride + threadIdx.x, r < nround, of a workgroup.
+__device__ inline void grid_levels_block(const double* __restrict__ x,
+                                         const double* __restrict__ y,
+                                         const double* __restrict__ z,
+                                         const double* __restrict__ h, int64_t ng,
+                                         sg_grid_dev* g, int64_t base, int64_t stride,
+                                         int64_t nround) {
     __shared__ unsigned long long s_lo[SG_MAXLEV][3], s_hi[SG_MAXLEV][3];
     __shared__ unsigned long long s_hmax[SG_MAXLEV], s_cnt[SG_MAXLEV];
     if (g->err & SGE_NONFINITE) return;   // uniform across the grid
@@ -247,10 +273,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_levels(const double* __restrict
     const double hmin = sg_unord(g->hmin_bits);
     const double L0 = pow2_ceil(hmin * (2.0 + 0x1p-9));
     bool bad = false;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t nround = (ng + stride - 1) / stride;
     for (int64_t r = 0; r < nround; ++r) {
-        int64_t i = r * stride + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        int64_t i = r * stride + base + threadIdx.x;
         bool valid = i < ng;
         int lev = -1;
         double p[3] = {0, 0, 0}, hi = 0;
@@ -301,10 +325,19 @@ __global__ __launch_bounds__(kBlock) void k_grid_levels(const double* __restrict
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_grid_levels(const double* __restrict__ x,
+                                                        const double* __restrict__ y,
+                                                        const double* __restrict__ z,
+                                                        const double* __restrict__ h,
+                                                        int64_t ng, sg_grid_dev* g) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    grid_levels_block(x, y, z, h, ng, g, (int64_t)blockIdx.x * kBlock, stride,
+                      (ng + stride - 1) / stride);
+}
+
 // Cell sides L[l] = L0 2^(l + cell_scale_log2) (powers of two); the level of
 // a particle depends on L0 only.
-__global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap, double cell_scale) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ inline void grid_finish_one(sg_grid_dev* g, int64_t cell_cap, double cell_scale) {
     if (g->err & (SGE_NONFINITE | SGE_LEVELS)) {
         g->M = 0;
         return;
@@ -365,31 +398,35 @@ __global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap, double cell_scal
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cells_clear(const sg_grid_dev* g,
-                                                        int32_t* __restrict__ count,
-                                                        unsigned long long* __restrict__ hmax,
-                                                        int32_t* __restrict__ cursor) {
+__global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap, double cell_scale) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    grid_finish_one(g, cell_cap, cell_scale);
+}
+
+__device__ inline void cells_clear_block(const sg_grid_dev* g, int32_t* __restrict__ count,
+                                         unsigned long long* __restrict__ hmax,
+                                         int32_t* __restrict__ cursor, int64_t b, int64_t nb) {
     if (g->err & SGE_SORT_FATAL) return;
     const int64_t M = g->M;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < M;
-         k += (int64_t)gridDim.x * kBlock) {
+    for (int64_t k = b * kBlock + threadIdx.x; k < M; k += nb * kBlock) {
         count[k] = 0;
         hmax[k] = 0ull;
         cursor[k] = 0;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_keys_count(const double* __restrict__ x,
-                                                       const double* __restrict__ y,
-                                                       const double* __restrict__ z,
-                                                       const double* __restrict__ h,
-                                                       int64_t ng, const sg_grid_dev* g,
-                                                       int32_t* __restrict__ key,
-                                                       int32_t* __restrict__ count,
-                                                       unsigned long long* __restrict__ hmax) {
-    if (g->err & SGE_SORT_FATAL) return;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= ng) return;
+__global__ __launch_bounds__(kBlock) void k_cells_clear(const sg_grid_dev* g,
+                                                        int32_t* __restrict__ count,
+                                                        unsigned long long* __restrict__ hmax,
+                                                        int32_t* __restrict__ cursor) {
+    cells_clear_block(g, count, hmax, cursor, blockIdx.x, gridDim.x);
+}
+
+__device__ inline void keys_count_one(const double* __restrict__ x, const double* __restrict__ y,
+                                      const double* __restrict__ z, const double* __restrict__ h,
+                                      int64_t i, const sg_grid_dev* g, int32_t* __restrict__ key,
+                                      int32_t* __restrict__ count,
+                                      unsigned long long* __restrict__ hmax) {
     const double hi = h[i];
     const int l = level_of(hi, g->L0);
     const double p[3] = {x[i], y[i], z[i]};
@@ -407,9 +444,59 @@ __global__ __launch_bounds__(kBlock) void k_keys_count(const double* __restrict_
     atomicMax(&hmax[k], (unsigned long long)__builtin_bit_cast(long long, hi));
 }
 
+__global__ __launch_bounds__(kBlock) void k_keys_count(const double* __restrict__ x,
+                                                       const double* __restrict__ y,
+                                                       const double* __restrict__ z,
+                                                       const double* __restrict__ h,
+                                                       int64_t ng, const sg_grid_dev* g,
+                                                       int32_t* __restrict__ key,
+                                                       int32_t* __restrict__ count,
+                                                       unsigned long long* __restrict__ hmax) {
+    if (g->err & SGE_SORT_FATAL) return;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= ng) return;
+    keys_count_one(x, y, z, h, i, g, key, count, hmax);
+}
+
 // Place particles in their cell's slot range (any order), then fix the order
 // inside each cell to ascending particle id: the rank of particle i in its
 // cell is the number of smaller ids in the same cell range.
+__device__ inline void scatter_one(const int32_t* __restrict__ key, int64_t i,
+                                   const int64_t* __restrict__ off, int32_t* __restrict__ cursor,
+                                   int32_t* __restrict__ tmp) {
+    const int32_t k = key[i];
+    const int64_t slot = off[k] + atomicAdd(&cursor[k], 1);
+    tmp[slot] = (int32_t)i;
+}
+
+__device__ inline void rankfix_one(const int32_t* __restrict__ key, int64_t s,
+                                   const int64_t* __restrict__ off,
+                                   const int32_t* __restrict__ tmp, int32_t* __restrict__ perm) {
+    const int32_t i = tmp[s];
+    const int32_t k = key[i];
+    const int64_t lo = off[k], hi = off[k + 1];
+    int64_t r = 0;
+    for (int64_t t = lo; t < hi; ++t) r += tmp[t] < i;
+    perm[lo + r] = i;
+}
+
+__device__ inline void gather_one(const int32_t* __restrict__ perm, int64_t s,
+                                  const double* __restrict__ x, const double* __restrict__ y,
+                                  const double* __restrict__ z, const double* __restrict__ h,
+                                  const double* __restrict__ m, double* __restrict__ xs,
+                                  double* __restrict__ ys, double* __restrict__ zs,
+                                  double* __restrict__ hs, double* __restrict__ ms,
+                                  sg_prec* __restrict__ prec) {
+    const int32_t i = perm[s];
+    const double px = x[i], py = y[i], pz = z[i], ph = h[i], pm = m[i];
+    xs[s] = px;
+    ys[s] = py;
+    zs[s] = pz;
+    hs[s] = ph;
+    ms[s] = pm;
+    prec[s] = sg_prec{px, py, pz, ph, pm, {0.0, 0.0, 0.0}};
+}
+
 __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ key, int64_t ng,
                                                     const sg_grid_dev* g,
                                                     const int64_t* __restrict__ off,
@@ -418,9 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ 
     if (g->err & SGE_SORT_FATAL) return;
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= ng) return;
-    const int32_t k = key[i];
-    const int64_t slot = off[k] + atomicAdd(&cursor[k], 1);
-    tmp[slot] = (int32_t)i;
+    scatter_one(key, i, off, cursor, tmp);
 }
 
 __global__ __launch_bounds__(kBlock) void k_rankfix(const int32_t* __restrict__ key, int64_t ng,
@@ -431,12 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_rankfix(const int32_t* __restrict__ 
     if (g->err & SGE_SORT_FATAL) return;
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= ng) return;
-    const int32_t i = tmp[s];
-    const int32_t k = key[i];
-    const int64_t lo = off[k], hi = off[k + 1];
-    int64_t r = 0;
-    for (int64_t t = lo; t < hi; ++t) r += tmp[t] < i;
-    perm[lo + r] = i;
+    rankfix_one(key, s, off, tmp, perm);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_gas(
@@ -448,14 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_gas(
     if (g->err & SGE_SORT_FATAL) return;
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= ng) return;
-    const int32_t i = perm[s];
-    const double px = x[i], py = y[i], pz = z[i], ph = h[i], pm = m[i];
-    xs[s] = px;
-    ys[s] = py;
-    zs[s] = pz;
-    hs[s] = ph;
-    ms[s] = pm;
-    prec[s] = sg_prec{px, py, pz, ph, pm, {0.0, 0.0, 0.0}};
+    gather_one(perm, s, x, y, z, h, m, xs, ys, zs, hs, ms, prec);
 }
 
 // ------------------------------------------------------ Morton ordering --
@@ -470,27 +543,11 @@ __global__ void k_gbox_reset(sg_grid_dev* g) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_gbox(const double* __restrict__ x,
-                                                 const double* __restrict__ y,
-                                                 const double* __restrict__ z, int64_t n,
-                                                 sg_grid_dev* g) {
-    unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
-    bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        const double p[3] = {x[i], y[i], z[i]};
-        for (int d = 0; d < 3; ++d) {
-            if (!finite_d(p[d])) {
-                bad = true;
-                continue;
-            }
-            unsigned long long o = sg_ord(p[d]);
-            mn[d] = o < mn[d] ? o : mn[d];
-            mx[d] = o > mx[d] ? o : mx[d];
-        }
-    }
-    // wavefront, then workgroup, then one global atomic per bound and
-    // workgroup (same-address atomics from every wavefront serialise in L2)
+// Fold one thread's bounds into the grid record: wavefront, then
+// workgroup, then one global atomic per bound and workgroup (same-address
+// atomics from every wavefront serialise in L2).
+__device__ inline void gbox_fold(const unsigned long long (&mn)[3], const unsigned long long (&mx)[3],
+                                 bool bad, sg_grid_dev* g) {
     __shared__ unsigned long long s_lo[3][kBlock / 64], s_hi[3][kBlock / 64];
     const int w = threadIdx.x >> 6;
     for (int d = 0; d < 3; ++d) {
@@ -514,6 +571,34 @@ __global__ __launch_bounds__(kBlock) void k_gbox(const double* __restrict__ x,
     if (bad) atomicOr(&g->err, SGE_GNONFINITE);
 }
 
+__device__ inline void gbox_point(const double* __restrict__ x, const double* __restrict__ y,
+                                  const double* __restrict__ z, int64_t i,
+                                  unsigned long long (&mn)[3], unsigned long long (&mx)[3],
+                                  bool& bad) {
+    const double p[3] = {x[i], y[i], z[i]};
+    for (int d = 0; d < 3; ++d) {
+        if (!finite_d(p[d])) {
+            bad = true;
+            continue;
+        }
+        unsigned long long o = sg_ord(p[d]);
+        mn[d] = o < mn[d] ? o : mn[d];
+        mx[d] = o > mx[d] ? o : mx[d];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gbox(const double* __restrict__ x,
+                                                 const double* __restrict__ y,
+                                                 const double* __restrict__ z, int64_t n,
+                                                 sg_grid_dev* g) {
+    unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        gbox_point(x, y, z, i, mn, mx, bad);
+    gbox_fold(mn, mx, bad, g);
+}
+
 __device__ inline uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
     v &= 0x3ff;
     v = (v | (v << 16)) & 0x030000ffu;
@@ -523,14 +608,10 @@ __device__ inline uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
     return v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_morton_keys(const double* __restrict__ x,
-                                                        const double* __restrict__ y,
-                                                        const double* __restrict__ z, int64_t n,
-                                                        const sg_grid_dev* g,
-                                                        uint32_t* __restrict__ keys,
-                                                        int32_t* __restrict__ vals) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+__device__ inline void morton_key_one(const double* __restrict__ x, const double* __restrict__ y,
+                                      const double* __restrict__ z, int64_t i,
+                                      const sg_grid_dev* g, uint32_t* __restrict__ keys,
+                                      int32_t* __restrict__ vals) {
     double lo[3], ext = 0.0;
     for (int d = 0; d < 3; ++d) {
         lo[d] = sg_unord(g->glo[d]);
@@ -549,36 +630,53 @@ __global__ __launch_bounds__(kBlock) void k_morton_keys(const double* __restrict
     vals[i] = (int32_t)i;
 }
 
+__global__ __launch_bounds__(kBlock) void k_morton_keys(const double* __restrict__ x,
+                                                        const double* __restrict__ y,
+                                                        const double* __restrict__ z, int64_t n,
+                                                        const sg_grid_dev* g,
+                                                        uint32_t* __restrict__ keys,
+                                                        int32_t* __restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    morton_key_one(x, y, z, i, g, keys, vals);
+}
+
 // Morton keys have 30 bits: three passes of 10-bit digits.
 constexpr int kRadixBits = 10;
 constexpr int kBuckets = 1 << kRadixBits;
 constexpr int kRadixPasses = 3;
 
 // Digit histogram of one tile, stored digit-major: hist[d * ntiles + tile].
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
-                                                       int64_t n, int shift, int64_t ntiles,
-                                                       int32_t* __restrict__ hist) {
+__device__ inline void radix_hist_tile(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                       int64_t ntiles, int32_t* __restrict__ hist,
+                                       int64_t tile) {
     __shared__ int32_t s_h[kBuckets];
     for (int t = threadIdx.x; t < kBuckets; t += kBlock) s_h[t] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = tile * kRadixTile;
     for (int k = 0; k < kRadixItems; ++k) {
         int64_t i = base + k * kBlock + threadIdx.x;
         if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & (kBuckets - 1)], 1);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < kBuckets; t += kBlock)
-        hist[(int64_t)t * ntiles + blockIdx.x] = s_h[t];
+    for (int t = threadIdx.x; t < kBuckets; t += kBlock) hist[(int64_t)t * ntiles + tile] = s_h[t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                       int64_t n, int shift, int64_t ntiles,
+                                                       int32_t* __restrict__ hist) {
+    radix_hist_tile(keys, n, shift, ntiles, hist, blockIdx.x);
 }
 
 // Stable scatter: element order inside the tile is preserved within each
 // digit (chunk by chunk, wave by wave, lane by lane).  Per chunk, the first
 // lane of each (wave, digit) group publishes the group's size; after the
 // writes it adds that size to the digit's running count and clears its slot.
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
-    int64_t ntiles, const int64_t* __restrict__ offs, uint32_t* __restrict__ kout,
-    int32_t* __restrict__ vout) {
+__device__ inline void radix_scatter_tile(const uint32_t* __restrict__ kin,
+                                          const int32_t* __restrict__ vin, int64_t n, int shift,
+                                          int64_t ntiles, const int64_t* __restrict__ offs,
+                                          uint32_t* __restrict__ kout,
+                                          int32_t* __restrict__ vout, int64_t tile) {
     __shared__ int32_t s_run[kBuckets];
     __shared__ int32_t s_w[kBlock / 64][kBuckets];
     const int wave = threadIdx.x >> 6;
@@ -587,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         for (int w = 0; w < kBlock / 64; ++w) s_w[w][t] = 0;
     }
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = tile * kRadixTile;
     for (int k = 0; k < kRadixItems; ++k) {
         const int64_t i = base + k * kBlock + threadIdx.x;
         const bool valid = i < n;
@@ -607,7 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         if (valid) {
             int32_t pre = 0;
             for (int w = 0; w < wave; ++w) pre += s_w[w][d];
-            const int64_t dest = offs[(int64_t)d * ntiles + blockIdx.x] + s_run[d] + pre + r;
+            const int64_t dest = offs[(int64_t)d * ntiles + tile] + s_run[d] + pre + r;
             kout[dest] = key;
             vout[dest] = val;
         }
@@ -618,6 +716,244 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
+    int64_t ntiles, const int64_t* __restrict__ offs, uint32_t* __restrict__ kout,
+    int32_t* __restrict__ vout) {
+    radix_scatter_tile(kin, vin, n, shift, ntiles, offs, kout, vout, blockIdx.x);
+}
+
+// ---------------------------------------- Morton order, all systems at once --
+// (see sg_seg in sg_internal.h).  The same stable order as the per-system
+// sort: the same keys, digits and stable scatter.
+
+__global__ void k_seg_gbox_reset(const sg_seg_sys* __restrict__ sys, int nsys) {
+    for (int k = threadIdx.x; k < nsys; k += blockDim.x) {
+        sg_grid_dev* g = sys[k].g;
+        for (int d = 0; d < 3; ++d) {
+            g->glo[d] = ~0ull;
+            g->ghi[d] = 0ull;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_gbox(const sg_seg_sys* __restrict__ sys,
+                                                     const int64_t* __restrict__ pfx, int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
+    bool bad = false;
+    const int64_t i = lb * kBlock + threadIdx.x;
+    if (i < S.n) gbox_point(S.x, S.y, S.z, i, mn, mx, bad);
+    gbox_fold(mn, mx, bad, S.g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_morton_keys(const sg_seg_sys* __restrict__ sys,
+                                                            const int64_t* __restrict__ pfx,
+                                                            int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    const int64_t i = lb * kBlock + threadIdx.x;
+    if (i < S.n) morton_key_one(S.x, S.y, S.z, i, S.g, S.mk0, S.mv0);
+}
+
+// pass p reads buffer p & 1 and writes the other one; the last pass writes
+// the values to the order
+__global__ __launch_bounds__(kBlock) void k_seg_radix_hist(const sg_seg_sys* __restrict__ sys,
+                                                           const int64_t* __restrict__ pfx,
+                                                           int nsys, int pass) {
+    int64_t tile;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &tile)];
+    radix_hist_tile((pass & 1) ? S.mk1 : S.mk0, S.n, kRadixBits * pass, S.ntiles, S.mhist, tile);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_radix_scatter(const sg_seg_sys* __restrict__ sys,
+                                                              const int64_t* __restrict__ pfx,
+                                                              int nsys, int pass) {
+    int64_t tile;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &tile)];
+    const bool odd = pass & 1;
+    int32_t* vout = pass == kRadixPasses - 1 ? S.order : (odd ? S.mv0 : S.mv1);
+    radix_scatter_tile(odd ? S.mk1 : S.mk0, odd ? S.mv1 : S.mv0, S.n, kRadixBits * pass,
+                       S.ntiles, S.moffs, odd ? S.mk0 : S.mk1, vout, tile);
+}
+
+// Exclusive scan of one system's digit histogram (1024 * ntiles counts)
+// into its offsets, one workgroup of 1024 lanes per system; offs[total] is
+// not needed by the scatter and not written.
+constexpr int kSegScanBlock = 1024;
+__global__ __launch_bounds__(kSegScanBlock) void k_seg_scan_hist(const sg_seg_sys* __restrict__ sys) {
+    const sg_seg_sys& S = sys[blockIdx.x];
+    const int64_t n = (int64_t)kBuckets * S.ntiles;
+    __shared__ int64_t s_w[kSegScanBlock / 64];
+    __shared__ int64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    constexpr int kItems = 4;
+    for (int64_t c0 = 0; c0 < n; c0 += (int64_t)kSegScanBlock * kItems) {
+        const int64_t i0 = c0 + (int64_t)threadIdx.x * kItems;
+        int64_t v[kItems], tsum = 0;
+        for (int k = 0; k < kItems; ++k) {
+            v[k] = i0 + k < n ? S.mhist[i0 + k] : 0;
+            tsum += v[k];
+        }
+        int64_t incl = tsum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t t = __shfl_up(incl, o, 64);
+            if (lane_id() >= (unsigned)o) incl += t;
+        }
+        if (lane_id() == 63) s_w[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        int64_t wbase = s_carry;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += s_w[w];
+        int64_t run = wbase + incl - tsum;
+        for (int k = 0; k < kItems; ++k) {
+            if (i0 + k < n) S.moffs[i0 + k] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t t = 0;
+            for (int w = 0; w < kSegScanBlock / 64; ++w) t += s_w[w];
+            s_carry += t;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------- gas sort, all systems at once --
+// (see sg_seg in sg_internal.h): the per-system kernels' bodies; a system
+// without gas is skipped, as the per-system build does.
+
+__global__ void k_seg_grid_reset(const sg_seg_sys* __restrict__ sys) {
+    const sg_seg_sys& S = sys[blockIdx.x];
+    if (S.ng > 0) grid_reset_one(S.g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_grid_hmin(const sg_seg_sys* __restrict__ sys,
+                                                          const int64_t* __restrict__ pfx,
+                                                          int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    unsigned long long mn = ~0ull;
+    bool bad = false;
+    const int64_t i = lb * kBlock + threadIdx.x;
+    if (i < S.ng) hmin_item(S.x, S.y, S.z, S.h, i, mn, bad);
+    hmin_fold(mn, bad, S.g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_grid_levels(const sg_seg_sys* __restrict__ sys,
+                                                            const int64_t* __restrict__ pfx,
+                                                            int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    grid_levels_block(S.x, S.y, S.z, S.h, S.ng, S.g, lb * kBlock, 0, 1);
+}
+
+__global__ void k_seg_grid_finish(const sg_seg_sys* __restrict__ sys, int nsys) {
+    for (int k = threadIdx.x; k < nsys; k += blockDim.x)
+        if (sys[k].ng > 0) grid_finish_one(sys[k].g, sys[k].cell_cap, sys[k].cell_scale);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_cells_clear(const sg_seg_sys* __restrict__ sys,
+                                                            const int64_t* __restrict__ pfx,
+                                                            int nsys) {
+    int64_t lb;
+    const int k = sg_seg_find(pfx, nsys, blockIdx.x, &lb);
+    const sg_seg_sys& S = sys[k];
+    cells_clear_block(S.g, S.count, S.hmax, S.cursor, lb, pfx[k + 1] - pfx[k]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_keys_count(const sg_seg_sys* __restrict__ sys,
+                                                           const int64_t* __restrict__ pfx,
+                                                           int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    if (S.g->err & SGE_SORT_FATAL) return;
+    const int64_t i = lb * kBlock + threadIdx.x;
+    if (i < S.ng) keys_count_one(S.x, S.y, S.z, S.h, i, S.g, S.key, S.count, S.hmax);
+}
+
+// which = 0: cell counts -> cell offsets (n = M from the grid, bounded by
+// the cell capacity); 1: neighbour counts -> CSR offsets (n = N_g)
+__device__ inline void seg_scan_args(const sg_seg_sys& S, int which, const int32_t** in,
+                                     int64_t** out, int64_t* n) {
+    if (which == 0) {
+        *in = S.count;
+        *out = S.off;
+        *n = S.g->M < S.cell_cap ? S.g->M : S.cell_cap;
+    } else {
+        *in = S.ncnt;
+        *out = const_cast<int64_t*>(S.sph.nbr_off);
+        *n = S.ng;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_scan_reduce(const sg_seg_sys* __restrict__ sys,
+                                                            const int64_t* __restrict__ pfx,
+                                                            int nsys, int which) {
+    int64_t tile;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &tile)];
+    const int32_t* in;
+    int64_t* out;
+    int64_t n;
+    seg_scan_args(S, which, &in, &out, &n);
+    scan_reduce_tile(in, n, tile, (int64_t*)S.scan);
+}
+
+__global__ __launch_bounds__(256) void k_seg_scan_bsums(const sg_seg_sys* __restrict__ sys,
+                                                        int which) {
+    const sg_seg_sys& S = sys[blockIdx.x];
+    if (S.ng == 0) return;
+    const int32_t* in;
+    int64_t* out;
+    int64_t n;
+    seg_scan_args(S, which, &in, &out, &n);
+    scan_bsums_block((int64_t*)S.scan, n, out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_scan_down(const sg_seg_sys* __restrict__ sys,
+                                                          const int64_t* __restrict__ pfx,
+                                                          int nsys, int which) {
+    int64_t tile;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &tile)];
+    const int32_t* in;
+    int64_t* out;
+    int64_t n;
+    seg_scan_args(S, which, &in, &out, &n);
+    scan_down_tile(in, out, n, tile, (const int64_t*)S.scan);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_scatter(const sg_seg_sys* __restrict__ sys,
+                                                        const int64_t* __restrict__ pfx, int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    if (S.g->err & SGE_SORT_FATAL) return;
+    const int64_t i = lb * kBlock + threadIdx.x;
+    if (i < S.ng) scatter_one(S.key, i, S.off, S.cursor, S.tmp);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_rankfix(const sg_seg_sys* __restrict__ sys,
+                                                        const int64_t* __restrict__ pfx, int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    if (S.g->err & SGE_SORT_FATAL) return;
+    const int64_t s = lb * kBlock + threadIdx.x;
+    if (s < S.ng) rankfix_one(S.key, s, S.off, S.tmp, const_cast<int32_t*>(S.sph.perm));
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_gather_gas(const sg_seg_sys* __restrict__ sys,
+                                                           const int64_t* __restrict__ pfx,
+                                                           int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    if (S.g->err & SGE_SORT_FATAL) return;
+    const int64_t s = lb * kBlock + threadIdx.x;
+    const sg_sph_bufs& b = S.sph;
+    if (s < S.ng)
+        gather_one(b.perm, s, S.x, S.y, S.z, S.h, S.m, b.xs, b.ys, b.zs, b.hs, b.ms, b.prec);
 }
 
 inline unsigned grid_for(int64_t n, int per_block) {
@@ -723,6 +1059,77 @@ size_t sg_morton_tmp_bytes(int64_t n) {
     size_t a, b, c, d, e, f, t;
     morton_layout(n, &a, &b, &c, &d, &e, &f, &t);
     return t;
+}
+
+int64_t sg_radix_tiles(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
+int64_t sg_scan_tiles(int64_t cap) { return grid_for(cap, kScanTile); }
+int64_t sg_cells_clear_blocks(int64_t cell_cap) {
+    const int64_t nb = grid_for(cell_cap, kBlock);
+    return nb > 256 ? 256 : nb;
+}
+
+static void seg_scan(const sg_seg& s, int which, hipStream_t st) {
+    const int q = which == 0 ? SG_SEG_SCAN_C : SG_SEG_SCAN_G;
+    const int64_t* p = s.pfx + q * (s.nsys + 1);
+    if (s.nblk[q] == 0) return;
+    hipLaunchKernelGGL(k_seg_scan_reduce, dim3((unsigned)s.nblk[q]), dim3(kBlock), 0, st, s.sys, p,
+                       s.nsys, which);
+    hipLaunchKernelGGL(k_seg_scan_bsums, dim3((unsigned)s.nsys), dim3(256), 0, st, s.sys, which);
+    hipLaunchKernelGGL(k_seg_scan_down, dim3((unsigned)s.nblk[q]), dim3(kBlock), 0, st, s.sys, p,
+                       s.nsys, which);
+}
+
+void sg_seg_launch_sort(const sg_seg& s, hipStream_t st) {
+    if (s.nblk[SG_SEG_NG] == 0) return;
+    const int64_t* png = s.pfx + SG_SEG_NG * (s.nsys + 1);
+    const int64_t* pcl = s.pfx + SG_SEG_CELLS * (s.nsys + 1);
+    const unsigned nbg = (unsigned)s.nblk[SG_SEG_NG];
+    hipLaunchKernelGGL(k_seg_grid_reset, dim3((unsigned)s.nsys), dim3(64), 0, st, s.sys);
+    hipLaunchKernelGGL(k_seg_grid_hmin, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
+    hipLaunchKernelGGL(k_seg_grid_levels, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
+    hipLaunchKernelGGL(k_seg_grid_finish, dim3(1), dim3(64), 0, st, s.sys, s.nsys);
+    hipLaunchKernelGGL(k_seg_cells_clear, dim3((unsigned)s.nblk[SG_SEG_CELLS]), dim3(kBlock), 0, st,
+                       s.sys, pcl, s.nsys);
+    hipLaunchKernelGGL(k_seg_keys_count, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
+    seg_scan(s, 0, st);
+    hipLaunchKernelGGL(k_seg_scatter, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
+    hipLaunchKernelGGL(k_seg_rankfix, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
+    hipLaunchKernelGGL(k_seg_gather_gas, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
+}
+
+void sg_seg_launch_scan_nbr(const sg_seg& s, hipStream_t st) { seg_scan(s, 1, st); }
+
+void sg_morton_ptrs(void* tmp, int64_t n, uint32_t** k0, uint32_t** k1, int32_t** v0,
+                    int32_t** v1, int32_t** hist, int64_t** offs, int64_t* ntiles) {
+    size_t o_k1, o_v0, o_v1, o_hist, o_offs, o_scan, total;
+    morton_layout(n, &o_k1, &o_v0, &o_v1, &o_hist, &o_offs, &o_scan, &total);
+    char* base = (char*)tmp;
+    *k0 = (uint32_t*)base;
+    *k1 = (uint32_t*)(base + o_k1);
+    *v0 = (int32_t*)(base + o_v0);
+    *v1 = (int32_t*)(base + o_v1);
+    *hist = (int32_t*)(base + o_hist);
+    *offs = (int64_t*)(base + o_offs);
+    *ntiles = sg_radix_tiles(n);
+}
+
+void sg_seg_launch_morton_order(const sg_seg& s, hipStream_t st) {
+    const int64_t* pn = s.pfx + SG_SEG_N * (s.nsys + 1);
+    const int64_t* pt = s.pfx + SG_SEG_TILES * (s.nsys + 1);
+    if (s.nblk[SG_SEG_N] == 0) return;
+    hipLaunchKernelGGL(k_seg_gbox_reset, dim3(1), dim3(64), 0, st, s.sys, s.nsys);
+    hipLaunchKernelGGL(k_seg_gbox, dim3((unsigned)s.nblk[SG_SEG_N]), dim3(kBlock), 0, st, s.sys, pn,
+                       s.nsys);
+    hipLaunchKernelGGL(k_seg_morton_keys, dim3((unsigned)s.nblk[SG_SEG_N]), dim3(kBlock), 0, st,
+                       s.sys, pn, s.nsys);
+    for (int pass = 0; pass < kRadixPasses; ++pass) {
+        hipLaunchKernelGGL(k_seg_radix_hist, dim3((unsigned)s.nblk[SG_SEG_TILES]), dim3(kBlock), 0,
+                           st, s.sys, pt, s.nsys, pass);
+        hipLaunchKernelGGL(k_seg_scan_hist, dim3((unsigned)s.nsys), dim3(kSegScanBlock), 0, st,
+                           s.sys);
+        hipLaunchKernelGGL(k_seg_radix_scatter, dim3((unsigned)s.nblk[SG_SEG_TILES]), dim3(kBlock),
+                           0, st, s.sys, pt, s.nsys, pass);
+    }
 }
 
 void sg_launch_morton_order(const double* x, const double* y, const double* z, int64_t n,

@@ -77,11 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_density_f64(sg_sph_bufs b, const sg_
     rho_out[b.perm[s]] = acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_density_f32(sg_sph_bufs b, const sg_grid_dev* g,
-                                                        int64_t ng, double* __restrict__ rho_out) {
-    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (s >= ng) return;
+__device__ inline void density_f32_one(const sg_sph_bufs& b, int64_t s,
+                                       double* __restrict__ rho_out) {
     const sg_prec pi = b.prec[s];
     const float hi = (float)pi.h;
     kahan acc{(float)(pi.m / (kPi * pi.h * pi.h * pi.h)), 0.0f};
@@ -99,18 +96,22 @@ __global__ __launch_bounds__(kBlock) void k_density_f32(sg_sph_bufs b, const sg_
     rho_out[b.perm[s]] = rho;
 }
 
-// Pack the state the force pass should use (velocities and energies of the
-// current or predicted state) into one record per slot, with p / rho^2 and
-// the sound speed sqrt(gamma p / rho) from the ideal-gas law.
-__global__ __launch_bounds__(kBlock) void k_sph_prep(sg_sph_bufs b, const sg_grid_dev* g,
-                                                     int64_t ng, int precision, double gamma,
-                                                     const double* __restrict__ vx,
-                                                     const double* __restrict__ vy,
-                                                     const double* __restrict__ vz,
-                                                     const double* __restrict__ e) {
+__global__ __launch_bounds__(kBlock) void k_density_f32(sg_sph_bufs b, const sg_grid_dev* g,
+                                                        int64_t ng, double* __restrict__ rho_out) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
     const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (s >= ng) return;
+    density_f32_one(b, s, rho_out);
+}
+
+// Pack the state the force pass should use (velocities and energies of the
+// current or predicted state) into one record per slot, with p / rho^2 and
+// the sound speed sqrt(gamma p / rho) from the ideal-gas law.
+__device__ inline void sph_prep_one(const sg_sph_bufs& b, int64_t s, int precision,
+                                    double gamma, const double* __restrict__ vx,
+                                    const double* __restrict__ vy,
+                                    const double* __restrict__ vz,
+                                    const double* __restrict__ e) {
     const int32_t i = b.perm[s];
     const sg_prec q = b.prec[s];
     const double rho = b.rho_s[s];
@@ -135,6 +136,18 @@ __global__ __launch_bounds__(kBlock) void k_sph_prep(sg_sph_bufs b, const sg_gri
     } else {
         b.f64[s] = sg_frec64{q.x, q.y, q.z, q.h, q.m, vx[i], vy[i], vz[i], rho, P, c, 0.0};
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sph_prep(sg_sph_bufs b, const sg_grid_dev* g,
+                                                     int64_t ng, int precision, double gamma,
+                                                     const double* __restrict__ vx,
+                                                     const double* __restrict__ vy,
+                                                     const double* __restrict__ vz,
+                                                     const double* __restrict__ e) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    sph_prep_one(b, s, precision, gamma, vx, vy, vz, e);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sph_force_f64(sg_sph_bufs b, const sg_grid_dev* g,
@@ -184,15 +197,10 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f64(sg_sph_bufs b, const s
     dedt[i] = 0.5 * se;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const sg_grid_dev* g,
-                                                          int64_t ng, float alpha, float beta,
-                                                          float eta, double* __restrict__ asx,
-                                                          double* __restrict__ asy,
-                                                          double* __restrict__ asz,
-                                                          double* __restrict__ dedt) {
-    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (s >= ng) return;
+__device__ inline void sph_force_f32_one(const sg_sph_bufs& b, int64_t s, float alpha,
+                                         float beta, float eta, double* __restrict__ asx,
+                                         double* __restrict__ asy, double* __restrict__ asz,
+                                         double* __restrict__ dedt) {
     const sg_frec32 a = b.f32[s];
     const float kgrad = (float)(-45.0 / (64.0 * kPi));
     kahan sx{0, 0}, sy{0, 0}, sz{0, 0}, se{0, 0};
@@ -228,6 +236,56 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const s
     asy[i] = sy.value();
     asz[i] = sz.value();
     dedt[i] = 0.5 * se.value();
+}
+
+__global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const sg_grid_dev* g,
+                                                          int64_t ng, float alpha, float beta,
+                                                          float eta, double* __restrict__ asx,
+                                                          double* __restrict__ asy,
+                                                          double* __restrict__ asz,
+                                                          double* __restrict__ dedt) {
+    if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (s >= ng) return;
+    sph_force_f32_one(b, s, alpha, beta, eta, asx, asy, asz, dedt);
+}
+
+// Density, EOS records and the FP32C force pass for every system of an
+// ensemble (blocks of 256 gas slots per system); the records take the
+// current state, or the predicted one (predicted != 0).
+__global__ __launch_bounds__(kBlock) void k_seg_density(const sg_seg_sys* __restrict__ sys,
+                                                        const int64_t* __restrict__ pfx,
+                                                        int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    if (S.g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = lb * kBlock + threadIdx.x;
+    if (s >= S.ng) return;
+    density_f32_one(S.sph, s, S.rho);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_sph_prep(const sg_seg_sys* __restrict__ sys,
+                                                         const int64_t* __restrict__ pfx,
+                                                         int nsys, int predicted) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    if (S.g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = lb * kBlock + threadIdx.x;
+    if (s >= S.ng) return;
+    if (predicted) sph_prep_one(S.sph, s, SG_FP32C, S.gamma, S.vtx, S.vty, S.vtz, S.et);
+    else sph_prep_one(S.sph, s, SG_FP32C, S.gamma, S.vx, S.vy, S.vz, S.e);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_sph_force(const sg_seg_sys* __restrict__ sys,
+                                                          const int64_t* __restrict__ pfx,
+                                                          int nsys) {
+    int64_t lb;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
+    if (S.g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
+    const int64_t s = lb * kBlock + threadIdx.x;
+    if (s >= S.ng) return;
+    sph_force_f32_one(S.sph, s, (float)S.alpha, (float)S.beta, (float)S.eta, S.asx, S.asy, S.asz,
+                      S.dedt);
 }
 
 // Step control of Sec. 2.2.  CFL bound of Eq. (dt-stability) per gas slot,
@@ -323,6 +381,22 @@ void sg_launch_sph_force(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng,
     else
         hipLaunchKernelGGL(k_sph_force_f64, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng,
                            alpha, beta, eta, asx, asy, asz, dedt);
+}
+
+void sg_seg_launch_density(const sg_seg& s, int beside_grav, hipStream_t st) {
+    if (s.nblk[SG_SEG_NG] == 0) return;
+    hipLaunchKernelGGL(k_seg_density, dim3((unsigned)s.nblk[SG_SEG_NG]), dim3(kBlock),
+                       beside_grav ? 0u : kGatherLds, st, s.sys, s.pfx + SG_SEG_NG * (s.nsys + 1),
+                       s.nsys);
+}
+
+void sg_seg_launch_sph_state(const sg_seg& s, int predicted, int beside_grav, hipStream_t st) {
+    if (s.nblk[SG_SEG_NG] == 0) return;
+    const int64_t* p = s.pfx + SG_SEG_NG * (s.nsys + 1);
+    hipLaunchKernelGGL(k_seg_sph_prep, dim3((unsigned)s.nblk[SG_SEG_NG]), dim3(kBlock), 0, st,
+                       s.sys, p, s.nsys, predicted);
+    hipLaunchKernelGGL(k_seg_sph_force, dim3((unsigned)s.nblk[SG_SEG_NG]), dim3(kBlock),
+                       beside_grav ? 0u : kGatherLds, st, s.sys, p, s.nsys);
 }
 
 void sg_launch_cfl(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, double alpha,

@@ -134,8 +134,7 @@ def lib():
     L.sg_ensemble_bytes.restype = C.c_size_t
     L.sg_ensemble_bytes.argtypes = [i32, i64]
     L.sg_ensemble_create.restype = C.c_int
-    L.sg_ensemble_create.argtypes = [C.POINTER(vp), i32, vp, C.c_size_t, C.POINTER(vp), i32, vp,
-                                     C.POINTER(vp)]
+    L.sg_ensemble_create.argtypes = [C.POINTER(vp), i32, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.sg_ensemble_gravity.restype = C.c_int
     L.sg_ensemble_gravity.argtypes = [vp, u32]
     L.sg_ensemble_step.restype = C.c_int
@@ -445,20 +444,11 @@ class Ensemble:
     """Independent systems (one Engine each, FP32C, one shared stream) whose
     gravity runs as one persistent launch."""
 
-    def __init__(self, states, device="cuda", **kw):
+    def __init__(self, states, device="cuda", grav_stream=None, **kw):
         import torch
         self.torch = torch
         dev = torch.device(device)
         self.stream = torch.cuda.Stream(device=dev)
-        # the systems' own launches run side by side on up to 8 torch
-        # streams (distinct from the shared one); the batched gravity gets
-        # the library's CU-masked stream (grav_stream NULL)
-        self.side = []
-        for _ in range(min(8, len(states))):
-            x = torch.cuda.Stream(device=dev)
-            if x.cuda_stream != self.stream.cuda_stream and all(
-                    x.cuda_stream != y.cuda_stream for y in self.side):
-                self.side.append(x)
         self.engines = [Engine(st, precision=SG_FP32C, device=device, stream=self.stream,
                                aux_stream=None, **kw) for st in states]
         total = sum(e.n for e in self.engines)
@@ -469,9 +459,14 @@ class Ensemble:
         handles = (C.c_void_p * len(self.engines))(*[e.ctx.h.value for e in self.engines])
         h = C.c_void_p()
         torch.cuda.synchronize()
-        side = (C.c_void_p * max(1, len(self.side)))(*[x.cuda_stream for x in self.side])
-        rc = L.sg_ensemble_create(handles, len(self.engines), C.c_void_p(ptr), nbytes, side,
-                                  len(self.side), None, C.byref(h))
+        # grav_stream: None = the library's CU-masked stream, "new" = a torch
+        # stream, or a torch stream
+        if grav_stream == "new":
+            grav_stream = torch.cuda.Stream(device=dev)
+        self.grav_stream = grav_stream
+        gs = C.c_void_p(grav_stream.cuda_stream) if grav_stream is not None else None
+        rc = L.sg_ensemble_create(handles, len(self.engines), C.c_void_p(ptr), nbytes, gs,
+                                  C.byref(h))
         if rc != SG_OK:
             raise SGError(rc, "sg_ensemble_create failed")
         self.h = h

@@ -51,12 +51,12 @@ def test_ensemble_create_rejects_mismatched_contexts(sg, states, other):
     handles = (C.c_void_p * 2)(a.ctx.h.value, b.ctx.h.value)
     h = C.c_void_p()
     torch.cuda.synchronize()
-    rc = L.sg_ensemble_create(handles, 2, C.c_void_p(ptr), nbytes, None, 0, None, C.byref(h))
+    rc = L.sg_ensemble_create(handles, 2, C.c_void_p(ptr), nbytes, None, C.byref(h))
     assert rc == sg.SG_EINVAL and not h.value
     # the same two systems with matching contexts are accepted
     b_ok = sg.Engine(states[1], precision=sg.SG_FP32C, stream=stream)
     handles = (C.c_void_p * 2)(a.ctx.h.value, b_ok.ctx.h.value)
-    assert L.sg_ensemble_create(handles, 2, C.c_void_p(ptr), nbytes, None, 0, None,
+    assert L.sg_ensemble_create(handles, 2, C.c_void_p(ptr), nbytes, None,
                                 C.byref(h)) == sg.SG_OK
     L.sg_ensemble_destroy(h)
 
