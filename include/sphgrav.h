@@ -18,12 +18,12 @@
  *   stream given to sg_create(); entry points return as soon as the work
  *   is enqueued.  Only sg_status_sync(), sg_export(), sg_profile_read(),
  *   sg_run(), sg_ensemble_create(), sg_ensemble_run() and the destroy calls
- *   wait for streams.  Inside a step the gravity runs on the caller's
- *   second (auxiliary) stream when one was given, forked from the main
- *   stream and joined back into it before the step's last kernels, so
- *   every step stays ordered on the main stream (and can be captured from
- *   it).  The library creates only the events of those forks and joins,
- *   and, for an ensemble given no gravity stream, one CU-masked stream
+ *   wait for streams.  Inside a step the neighbour/SPH chain runs on the
+ *   caller's second (auxiliary) stream when one was given, beside the
+ *   gravity on the main stream: forked from the main stream and joined back
+ *   into it before the step's last kernels, so every step stays ordered on
+ *   the main stream (and can be captured from it).  The library creates only the events of those forks and joins,
+ *   and, for an ensemble given no chain stream, one CU-masked stream
  *   (sg_ensemble_create).
  * - Errors: every call returns an sg_status; nothing aborts and no C++
  *   exception crosses the ABI.  Argument errors are detected on the host
@@ -102,8 +102,9 @@ typedef enum {
  *   side L0 * 2^(l + cell_scale_log2).  It changes cell keys, counts,
  *   offsets and the slot order (so the exported grid arrays and the order
  *   of SPH sums), never which particles are neighbours.
- * step_serial: 0 = in a step, gravity runs on the context's auxiliary stream
- *   beside the neighbours -> density -> SPH(corrector) chain (default);
+ * step_serial: 0 = in a step, the neighbours -> density -> SPH(corrector)
+ *   chain runs on the context's auxiliary stream beside the gravity
+ *   (default);
  *   1 = the two one after the other on the context's stream (for kernel
  *   traces whose per-kernel durations should not include waiting beside
  *   the gravity kernel).  Results are the same either way, bit for bit.
@@ -158,9 +159,9 @@ size_t sg_workspace_bytes(const sg_params *prm, const sg_caps *caps);
 /* Create a context over a caller-owned workspace of ws_bytes bytes
  * (>= sg_workspace_bytes, 256-byte aligned) on HIP stream `stream`
  * (a hipStream_t; NULL = the default stream).  aux_stream: a second
- * caller-owned stream (hipStream_t) on which each step runs the gravity
- * beside the neighbour/SPH chain; NULL or equal to `stream`: the two run
- * one after the other on `stream` (as with step_serial).  Both streams and
+ * caller-owned stream (hipStream_t) on which each step runs the
+ * neighbour/SPH chain beside the gravity; NULL or equal to `stream`: the
+ * two run one after the other on `stream` (as with step_serial).  Both streams and
  * the workspace must outlive the context (sg_destroy waits for both
  * streams).  Enqueues a clear of the device status.  On failure *out is
  * NULL and sg_last_error(NULL) says why. */
@@ -236,10 +237,10 @@ sg_status sg_kick_drift(sg_ctx *ctx, double dt, int32_t phase);
 /* One whole step, enqueue-only: [first call: neighbours, density,
  * gravity] -> SPH(predictor) -> SG_PREDICT -> neighbours -> density ->
  * gravity (once per step, reused by the next predictor) -> SPH(corrector)
- * -> SG_CORRECT.  After SG_PREDICT the gravity runs on the context's
- * auxiliary stream beside the neighbours -> density -> SPH(corrector) chain
- * (the two are independent); results equal the sequential order bit for
- * bit.  flags may add SG_POT. */
+ * -> SG_CORRECT.  After SG_PREDICT the neighbours -> density ->
+ * SPH(corrector) chain runs on the context's auxiliary stream beside the
+ * gravity (the two are independent); results equal the sequential order
+ * bit for bit.  flags may add SG_POT. */
 sg_status sg_step(sg_ctx *ctx, double dt, uint32_t flags);
 
 /* nsteps whole steps (as sg_step) with the conserved quantities of each
@@ -339,27 +340,28 @@ sg_status sg_status_sync(sg_ctx *ctx, int64_t need[2]);
  * them while it exists.  d_ws: caller-owned device memory of
  * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task and
  * system tables are uploaded once, synchronously, by sg_ensemble_create.
- * grav_stream: the caller's stream (not the contexts' stream) for the
- * batched gravity beside the systems' corrector chains, or NULL: then the
- * ensemble creates (and destroys) one stream with every CU in its mask,
+ * chain_stream: the caller's stream (not the contexts' stream) on which the
+ * systems' corrector chains run beside the batched gravity, or NULL: then
+ * the ensemble creates (and destroys) one stream with every CU in its mask,
  * because a stream of that kind gets a hardware queue of its own, where an
  * ordinary stream may share a queue with the contexts' stream and hold the
- * chains' launches behind the long gravity kernel.  The stream must
- * outlive the ensemble. */
+ * chains behind the long gravity kernel.  The stream must outlive the
+ * ensemble. */
 typedef struct sg_ens sg_ens;   /* opaque */
 size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles);
 sg_status sg_ensemble_create(sg_ctx *const *ctxs, int32_t nsys, void *d_ws, size_t ws_bytes,
-                             void *grav_stream, sg_ens **out);
+                             void *chain_stream, sg_ens **out);
 /* Batched gravity (flags SG_GRAV [| SG_POT]) for every system, then each
  * context's acceleration output is refreshed as in sg_compute_accel. */
 sg_status sg_ensemble_gravity(sg_ens *e, uint32_t flags);
 /* One predictor-corrector step of every system (as sg_step), gravity
  * batched, on the contexts' stream; after SG_PREDICT the batched gravity
- * runs on the gravity stream, forked from the contexts' stream and joined
- * back into it, beside the systems' neighbours -> density ->
- * SPH(corrector) chains.  With step_serial (of the first context) the
- * gravity runs on the contexts' stream before the chains.  Results equal
- * those of sg_step on each context alone (same launch shape) bit for bit. */
+ * runs there while the systems' neighbours -> density -> SPH(corrector)
+ * chains run beside it on the chain stream, forked from the contexts'
+ * stream before the gravity launch and joined back after the chains.  With
+ * step_serial (of the first context) the chains follow the gravity on the
+ * contexts' stream.  Results equal those of sg_step on each context alone
+ * (same launch shape) bit for bit. */
 sg_status sg_ensemble_step(sg_ens *e, double dt, uint32_t flags);
 /* nsteps ensemble steps; with use_graph one period of steady-state steps
  * is captured once and replayed (as sg_run).  Waits for the stream. */

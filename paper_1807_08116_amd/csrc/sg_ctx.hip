@@ -47,8 +47,8 @@ int64_t part_cap_elems(int64_t n) {
 
 struct layout {
     size_t grid;
-    size_t key, perm, tmp;
-    size_t count, cursor, hmax, off;
+    size_t key, perm, gsort;
+    size_t count, hmax, off;
     size_t scan;
     size_t xs, ys, zs, hs, ms, rho_s, prec, f64, f32;
     size_t ncnt, nbr_off, nbr_idx, nbr_slots;
@@ -75,9 +75,8 @@ layout make_layout(const sg_params* p, const sg_caps* c) {
     L.grid = take(sizeof(sg_grid_dev));
     L.key = take(4 * ng);
     L.perm = take(4 * ng);
-    L.tmp = take(4 * ng);
+    L.gsort = take(sg_morton_tmp_bytes(ng));   // radix sort of the cell keys
     L.count = take(4 * C);
-    L.cursor = take(4 * C);
     L.hmax = take(8 * C);
     L.off = take(8 * (C + 1));
     L.scan = take(sg_scan_tmp_bytes(C > ng + 1 ? C : ng + 1));
@@ -326,7 +325,6 @@ sg_status do_build(sg_ctx* c) {
     const int64_t C = c->caps.cell_cap;
     int32_t* key = c->at<int32_t>(c->L.key);
     int32_t* count = c->at<int32_t>(c->L.count);
-    int32_t* cursor = c->at<int32_t>(c->L.cursor);
     unsigned long long* hmax = c->at<unsigned long long>(c->L.hmax);
     int64_t* off = c->at<int64_t>(c->L.off);
     void* scan = c->at<void>(c->L.scan);
@@ -335,11 +333,10 @@ sg_status do_build(sg_ctx* c) {
     sg_launch_grid_reset(g, st);
     sg_launch_grid_reduce(s.x, s.y, s.z, s.h, ng, g, st);
     sg_launch_grid_finish(g, C, c->prm.cell_scale_log2, st);
-    sg_launch_cells_clear(g, count, hmax, cursor, C, st);
+    sg_launch_cells_clear(g, count, hmax, C, st);
     sg_launch_keys_count(s.x, s.y, s.z, s.h, ng, g, key, count, hmax, st);
     sg_launch_scan(count, off, 0, &g->M, C, scan, st);
-    sg_launch_scatter_rank(key, ng, g, off, cursor, c->at<int32_t>(c->L.tmp),
-                           c->at<int32_t>(c->L.perm), st);
+    sg_launch_gas_order(key, ng, C, c->at<void>(c->L.gsort), c->at<int32_t>(c->L.perm), st);
     sg_launch_gather_gas(b.perm, ng, g, s.x, s.y, s.z, s.h, s.m, b.xs, b.ys, b.zs, b.hs, b.ms,
                          b.prec, st);
     c->end();
@@ -542,10 +539,14 @@ sg_status do_step(sg_ctx* c, double dt, uint32_t flags) {
     if ((r = do_kick_drift(c, dt, SG_PREDICT)) != SG_OK) return r;
     // corrector right-hand side.  Gravity at the predicted positions and the
     // neighbour build -> density -> SPH forces chain are independent: with a
-    // second stream, gravity runs there (forked from and joined back into
-    // the context's stream, also while it is being captured) and the chain
-    // on the context's stream.  They touch disjoint workspace buffers and
+    // second stream, the chain runs there (forked from the context's stream
+    // before the gravity is enqueued on it, and joined back, also while the
+    // stream is being captured).  They touch disjoint workspace buffers and
     // disjoint fields of the grid record (the status word by atomic OR).
+    // Gravity first on the context's stream: measured on ensembles, the
+    // persistent gravity kernel keeps its pace when its workgroups are
+    // dispatched ahead of the chain's, and loses 14 % when the chain's come
+    // first.
     if (!c->st2 || c->prm.step_serial) {
         if ((r = do_build(c)) != SG_OK) return r;
         if ((r = do_density(c)) != SG_OK) return r;
@@ -554,20 +555,20 @@ sg_status do_step(sg_ctx* c, double dt, uint32_t flags) {
     }
     if (hipEventRecord(c->ev_fork, c->st) != hipSuccess ||
         hipStreamWaitEvent(c->st2, c->ev_fork, 0) != hipSuccess)
-        return c->fail(SG_EDEVICE, "step: fork to the gravity stream failed");
+        return c->fail(SG_EDEVICE, "step: fork to the second stream failed");
+    sg_status rg = do_gravity(c, (flags & SG_POT) != 0);
     hipStream_t own = c->st;
     c->st = c->st2;
-    sg_status rg = do_gravity(c, (flags & SG_POT) != 0);
-    c->st = own;
     c->beside_grav = true;
     sg_status rs = rg != SG_OK ? rg : do_build(c);
     if (rs == SG_OK) rs = do_density(c);
     if (rs == SG_OK) rs = do_sph(c);
     c->beside_grav = false;
+    c->st = own;
     // join (also after an error, so that a capture stays whole)
     if ((hipEventRecord(c->ev_join, c->st2) != hipSuccess ||
          hipStreamWaitEvent(c->st, c->ev_join, 0) != hipSuccess) && rs == SG_OK)
-        rs = c->fail(SG_EDEVICE, "step: join of the gravity stream failed");
+        rs = c->fail(SG_EDEVICE, "step: join of the second stream failed");
     if (rs != SG_OK) return rs;
     do_combine(c);
     c->accel_after_predict = true;
@@ -1016,12 +1017,13 @@ sg_status sg_status_sync(sg_ctx* c, int64_t need[2]) {
 struct sg_ens {
     std::vector<sg_ctx*> c;
     hipStream_t st;
-    // the batched gravity kernel's stream with its fork/join events: the
-    // caller's, or one the ensemble creates with every CU in its mask
-    // (which gives it a hardware queue of its own; own_gst)
-    hipStream_t gst;
-    bool own_gst;
-    hipEvent_t gev[2];
+    // the stream of the systems' corrector chains beside the batched
+    // gravity, with its fork/join events: the caller's, or one the ensemble
+    // creates with every CU in its mask (which gives it a hardware queue of
+    // its own; own_cst)
+    hipStream_t cst;
+    bool own_cst;
+    hipEvent_t cev[2];
     sg_ens_sys* d_sys;
     sg_ens_task* d_tasks;
     int32_t* d_counter;
@@ -1036,9 +1038,9 @@ struct sg_ens {
     }
     ~sg_ens() {
         if (st) (void)hipStreamSynchronize(st);
-        if (gst) (void)hipStreamSynchronize(gst);
-        if (gst && own_gst) (void)hipStreamDestroy(gst);
-        for (hipEvent_t x : gev)
+        if (cst) (void)hipStreamSynchronize(cst);
+        if (cst && own_cst) (void)hipStreamDestroy(cst);
+        for (hipEvent_t x : cev)
             if (x) (void)hipEventDestroy(x);
     }
 };
@@ -1203,7 +1205,7 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
     // gravity kernel reads only the prepared inputs), or before them with
     // step_serial (of the first context)
     auto chains = [&]() {
-        const bool beside = !c0->prm.step_serial && e->gst;
+        const bool beside = !c0->prm.step_serial && e->cst;
         sg_status q = ens_lists_density(e, beside);
         if (q != SG_OK) return q;
         c0->begin(SG_ST_SPH);
@@ -1212,19 +1214,26 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
         for (sg_ctx* c : e->c) c->have_sph = true;
         return ens_launched(e, "SPH forces");
     };
-    if (c0->prm.step_serial || !e->gst) {
+    if (c0->prm.step_serial || !e->cst) {
         if ((r = ens_grav_launch(e, pot, e->st)) != SG_OK) return r;
         if ((r = chains()) != SG_OK) return r;
     } else {
-        if (hipEventRecord(e->gev[0], e->st) != hipSuccess ||
-            hipStreamWaitEvent(e->gst, e->gev[0], 0) != hipSuccess)
-            return e->fail(SG_EDEVICE, "fork to the gravity stream failed");
-        r = ens_grav_launch(e, pot, e->gst);
+        // the gravity on the contexts' stream, the chains on the second one
+        // (forked before the gravity launch, joined back after the chains)
+        if (hipEventRecord(e->cev[0], e->st) != hipSuccess ||
+            hipStreamWaitEvent(e->cst, e->cev[0], 0) != hipSuccess)
+            return e->fail(SG_EDEVICE, "fork to the chain stream failed");
+        r = ens_grav_launch(e, pot, e->st);
+        hipStream_t own = e->st;
+        for (sg_ctx* c : e->c) c->st = e->cst;
+        e->st = e->cst;
         sg_status rc = r == SG_OK ? chains() : r;
+        e->st = own;
+        for (sg_ctx* c : e->c) c->st = own;
         // join (also after an error, so that a capture stays whole)
-        if ((hipEventRecord(e->gev[1], e->gst) != hipSuccess ||
-             hipStreamWaitEvent(e->st, e->gev[1], 0) != hipSuccess) && rc == SG_OK)
-            rc = e->fail(SG_EDEVICE, "join of the gravity stream failed");
+        if ((hipEventRecord(e->cev[1], e->cst) != hipSuccess ||
+             hipStreamWaitEvent(e->st, e->cev[1], 0) != hipSuccess) && rc == SG_OK)
+            rc = e->fail(SG_EDEVICE, "join of the chain stream failed");
         if (rc != SG_OK) return rc;
     }
     // corrector update, one launch each for all systems
@@ -1249,17 +1258,18 @@ size_t sg_ensemble_bytes(int32_t nsys, int64_t total_particles) {
 }
 
 sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size_t ws_bytes,
-                             void* grav_stream, sg_ens** out) {
+                             void* chain_stream, sg_ens** out) {
     if (!out || !ctxs || nsys < 1) return SG_EINVAL;
     *out = nullptr;
     if (!d_ws || ((uintptr_t)d_ws & (kAlign - 1))) return SG_EINVAL;
     if (!ctxs[0] || !ctxs[0]->bound) return SG_EINVAL;
-    if (grav_stream && grav_stream == (void*)ctxs[0]->st) return SG_EINVAL;
+    if (chain_stream && chain_stream == (void*)ctxs[0]->st) return SG_EINVAL;
     std::vector<sg_ens_sys> sys((size_t)nsys);
     std::vector<sg_seg_sys> seg((size_t)nsys);
     std::vector<int64_t> pfx((size_t)SG_SEG_NPFX * (nsys + 1), 0);
     std::vector<std::pair<int64_t, sg_ens_task>> tasks;
     int64_t total = 0;
+    int gas_passes = 1;
     // launch shape of the first context: 256 * ipl targets per task.  Unset
     // fields take the batched launch's measured best at 64 systems of
     // 8192-262144 particles, 2 targets per lane and 512 sources per tile
@@ -1306,8 +1316,8 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
         Q.h = c->s.h;
         Q.key = c->at<int32_t>(c->L.key);
         Q.count = c->at<int32_t>(c->L.count);
-        Q.cursor = c->at<int32_t>(c->L.cursor);
-        Q.tmp = c->at<int32_t>(c->L.tmp);
+        sg_morton_ptrs(c->at<void>(c->L.gsort), c->ng, &Q.gk0, &Q.gk1, &Q.gv0, &Q.gv1, &Q.ghist,
+                       &Q.goffs, &Q.gntiles);
         Q.ncnt = c->at<int32_t>(c->L.ncnt);
         Q.slots = c->at<int32_t>(c->L.nbr_slots);
         Q.hmax = c->at<unsigned long long>(c->L.hmax);
@@ -1350,7 +1360,10 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
                                           gas ? sg_cells_clear_blocks(c->caps.cell_cap) : 0,
                                           gas ? sg_scan_tiles(c->caps.cell_cap) : 0,
                                           gas ? sg_scan_tiles(c->ng) : 0,
-                                          (c->ng + 3) / 4};
+                                          (c->ng + 3) / 4,
+                                          gas ? Q.gntiles : 0};
+        if (gas && sg_gas_radix_passes(c->caps.cell_cap) > gas_passes)
+            gas_passes = sg_gas_radix_passes(c->caps.cell_cap);
         for (int q = 0; q < SG_SEG_NPFX; ++q)
             pfx[(size_t)q * (nsys + 1) + k + 1] = pfx[(size_t)q * (nsys + 1) + k] + cnt[q];
     }
@@ -1378,31 +1391,32 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
     e->seg.sys = (const sg_seg_sys*)(ws + o.seg);
     e->seg.pfx = (const int64_t*)(ws + o.pfx);
     e->seg.nsys = nsys;
+    e->seg.gas_passes = gas_passes;
     for (int q = 0; q < SG_SEG_NPFX; ++q) e->seg.nblk[q] = pfx[(size_t)q * (nsys + 1) + nsys];
     e->msg[0] = 0;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // the gravity stream: the caller's, else one with every CU in its mask.
+    // the chain stream: the caller's, else one with every CU in its mask.
     // A stream of the runtime's default kind shares one of the process's
     // few hardware queues with other streams, and a queue runs its packets
-    // in order, so the systems' launches enqueued behind the persistent
-    // gravity kernel in a shared queue would wait for it; a CU-masked
-    // stream gets a hardware queue of its own.
-    e->own_gst = grav_stream == nullptr;
-    if (grav_stream) {
-        e->gst = (hipStream_t)grav_stream;
+    // in order, so chains enqueued behind the persistent gravity kernel in a
+    // shared queue would wait for it; a CU-masked stream gets a hardware
+    // queue of its own.
+    e->own_cst = chain_stream == nullptr;
+    if (chain_stream) {
+        e->cst = (hipStream_t)chain_stream;
     } else {
         std::vector<uint32_t> mask((size_t)((cus > 0 ? cus : 256) + 31) / 32, 0xffffffffu);
         if (cus > 0 && cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
-        if (hipExtStreamCreateWithCUMask(&e->gst, (uint32_t)mask.size(), mask.data()) != hipSuccess)
-            e->gst = nullptr;
+        if (hipExtStreamCreateWithCUMask(&e->cst, (uint32_t)mask.size(), mask.data()) != hipSuccess)
+            e->cst = nullptr;
     }
-    if (!e->gst || hipEventCreateWithFlags(&e->gev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&e->gev[1], hipEventDisableTiming) != hipSuccess) {
-        if (e->gst && e->own_gst) (void)hipStreamDestroy(e->gst);   // fall back: gravity on st
-        e->gst = nullptr;
-        for (hipEvent_t& x : e->gev) {
+    if (!e->cst || hipEventCreateWithFlags(&e->cev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e->cev[1], hipEventDisableTiming) != hipSuccess) {
+        if (e->cst && e->own_cst) (void)hipStreamDestroy(e->cst);   // fall back: one stream
+        e->cst = nullptr;
+        for (hipEvent_t& x : e->cev) {
             if (x) (void)hipEventDestroy(x);
             x = nullptr;
         }

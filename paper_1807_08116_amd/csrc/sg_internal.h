@@ -102,13 +102,16 @@ void sg_launch_grid_reduce(const double* x, const double* y, const double* z, co
                            int64_t ng, sg_grid_dev* g, hipStream_t st);
 void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, int cell_scale_log2, hipStream_t st);
 void sg_launch_cells_clear(sg_grid_dev* g, int32_t* count, unsigned long long* hmax,
-                           int32_t* cursor, int64_t cell_cap, hipStream_t st);
+                           int64_t cell_cap, hipStream_t st);
 void sg_launch_keys_count(const double* x, const double* y, const double* z, const double* h,
                           int64_t ng, sg_grid_dev* g, int32_t* key, int32_t* count,
                           unsigned long long* hmax, hipStream_t st);
-void sg_launch_scatter_rank(const int32_t* key, int64_t ng, const sg_grid_dev* g,
-                            const int64_t* off, int32_t* cursor, int32_t* tmp, int32_t* perm,
-                            hipStream_t st);
+// Stable order of the gas by cell key (ascending id inside a cell): LSD
+// radix sort of the keys with 10-bit digits, enough passes for keys below
+// cell_cap; tmp: sg_morton_tmp_bytes(ng) bytes.
+int sg_gas_radix_passes(int64_t cell_cap);
+void sg_launch_gas_order(const int32_t* key, int64_t ng, int64_t cell_cap, void* tmp,
+                         int32_t* perm, hipStream_t st);
 struct sg_prec;
 void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
                           const double* x, const double* y, const double* z, const double* h,
@@ -247,7 +250,13 @@ struct sg_seg_sys {
     void* sbox;
     // gas sort and neighbour lists
     double* h;                       // caller's smoothing lengths
-    int32_t *key, *count, *cursor, *tmp, *ncnt, *slots;
+    int32_t *key, *count, *ncnt, *slots;
+    // radix sort of the cell keys (as the Morton buffers, for N_g)
+    uint32_t *gk0, *gk1;
+    int32_t *gv0, *gv1;
+    int32_t* ghist;
+    int64_t* goffs;
+    int64_t gntiles;
     unsigned long long* hmax;
     int64_t* off;
     void* scan;                      // scan scratch (block sums)
@@ -258,16 +267,17 @@ struct sg_seg_sys {
 // Block prefixes of a segmented launch, per system: blocks of 256
 // particles, of 256 gas particles, radix tiles, cell-clearing blocks
 // (grid-stride, at most 256 per system), scan tiles of the cell counts and
-// of the neighbour counts, and blocks of 4 gas particles (one wavefront
-// each).
+// of the neighbour counts, blocks of 4 gas particles (one wavefront each),
+// and radix tiles of the gas.
 enum {
     SG_SEG_N = 0, SG_SEG_NG = 1, SG_SEG_TILES = 2, SG_SEG_CELLS = 3, SG_SEG_SCAN_C = 4,
-    SG_SEG_SCAN_G = 5, SG_SEG_NG4 = 6, SG_SEG_NPFX = 7
+    SG_SEG_SCAN_G = 5, SG_SEG_NG4 = 6, SG_SEG_GTILES = 7, SG_SEG_NPFX = 8
 };
 struct sg_seg {
     const sg_seg_sys* sys;           // [nsys], device
     const int64_t* pfx;              // [SG_SEG_NPFX][nsys + 1] block prefixes, device
     int32_t nsys;
+    int32_t gas_passes;              // radix passes of the cell keys (largest over systems)
     int64_t nblk[SG_SEG_NPFX];       // totals of the prefixes (host)
 };
 // Host helpers for building the table.

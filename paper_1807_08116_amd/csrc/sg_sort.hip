@@ -404,44 +404,70 @@ __global__ void k_grid_finish(sg_grid_dev* g, int64_t cell_cap, double cell_scal
 }
 
 __device__ inline void cells_clear_block(const sg_grid_dev* g, int32_t* __restrict__ count,
-                                         unsigned long long* __restrict__ hmax,
-                                         int32_t* __restrict__ cursor, int64_t b, int64_t nb) {
+                                         unsigned long long* __restrict__ hmax, int64_t b,
+                                         int64_t nb) {
     if (g->err & SGE_SORT_FATAL) return;
     const int64_t M = g->M;
     for (int64_t k = b * kBlock + threadIdx.x; k < M; k += nb * kBlock) {
         count[k] = 0;
         hmax[k] = 0ull;
-        cursor[k] = 0;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_cells_clear(const sg_grid_dev* g,
                                                         int32_t* __restrict__ count,
-                                                        unsigned long long* __restrict__ hmax,
-                                                        int32_t* __restrict__ cursor) {
-    cells_clear_block(g, count, hmax, cursor, blockIdx.x, gridDim.x);
+                                                        unsigned long long* __restrict__ hmax) {
+    cells_clear_block(g, count, hmax, blockIdx.x, gridDim.x);
 }
 
-__device__ inline void keys_count_one(const double* __restrict__ x, const double* __restrict__ y,
-                                      const double* __restrict__ z, const double* __restrict__ h,
-                                      int64_t i, const sg_grid_dev* g, int32_t* __restrict__ key,
-                                      int32_t* __restrict__ count,
-                                      unsigned long long* __restrict__ hmax) {
-    const double hi = h[i];
-    const int l = level_of(hi, g->L0);
-    const double p[3] = {x[i], y[i], z[i]};
-    int64_t c[3];
-    for (int d = 0; d < 3; ++d) {
-        double v = floor((p[d] - g->org[l][d]) * g->invL[l]);
-        double top = (double)(g->dim[l][d] - 1);
-        v = v < 0.0 ? 0.0 : (v > top ? top : v);
-        c[d] = (int64_t)v;
+// Cell key of gas particle i, its count and the cell's maximum h.  Every
+// lane of the wavefront calls this (valid or not): the lanes that share the
+// key of the first valid lane add their count and maximum h with one
+// atomic each (clustered or coincident gas puts many particles of a
+// wavefront in one cell); the others add their own.
+__device__ inline void keys_count_wave(const double* __restrict__ x, const double* __restrict__ y,
+                                       const double* __restrict__ z,
+                                       const double* __restrict__ h, int64_t i, bool valid,
+                                       const sg_grid_dev* g, int32_t* __restrict__ key,
+                                       int32_t* __restrict__ count,
+                                       unsigned long long* __restrict__ hmax) {
+    int32_t k = -1;
+    unsigned long long hb = 0ull;
+    if (valid) {
+        const double hi = h[i];
+        const int l = level_of(hi, g->L0);
+        const double p[3] = {x[i], y[i], z[i]};
+        int64_t c[3];
+        for (int d = 0; d < 3; ++d) {
+            double v = floor((p[d] - g->org[l][d]) * g->invL[l]);
+            double top = (double)(g->dim[l][d] - 1);
+            v = v < 0.0 ? 0.0 : (v > top ? top : v);
+            c[d] = (int64_t)v;
+        }
+        k = (int32_t)(g->base[l] + (c[2] * g->dim[l][1] + c[1]) * g->dim[l][0] + c[0]);
+        key[i] = k;
+        hb = (unsigned long long)__builtin_bit_cast(long long, hi);   // h > 0: orders as bits
     }
-    const int32_t k =
-        (int32_t)(g->base[l] + (c[2] * g->dim[l][1] + c[1]) * g->dim[l][0] + c[0]);
-    key[i] = k;
-    atomicAdd(&count[k], 1);
-    atomicMax(&hmax[k], (unsigned long long)__builtin_bit_cast(long long, hi));
+    bool done = !valid;
+    const unsigned long long act = __ballot(valid);
+    if (act) {
+        const int lead = __builtin_ctzll(act);
+        const int32_t lk = __builtin_amdgcn_readlane(k, lead);
+        const unsigned long long peers = __ballot(valid && k == lk);
+        if (__builtin_popcountll(peers) > 1) {
+            const bool mine = (peers >> lane_id()) & 1ull;
+            const unsigned long long hm = wave_max_u64(mine ? hb : 0ull);
+            if ((int)lane_id() == lead) {
+                atomicAdd(&count[lk], (int32_t)__builtin_popcountll(peers));
+                atomicMax(&hmax[lk], hm);
+            }
+            done = done || mine;
+        }
+    }
+    if (!done) {
+        atomicAdd(&count[k], 1);
+        atomicMax(&hmax[k], hb);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_keys_count(const double* __restrict__ x,
@@ -453,33 +479,13 @@ __global__ __launch_bounds__(kBlock) void k_keys_count(const double* __restrict_
                                                        int32_t* __restrict__ count,
                                                        unsigned long long* __restrict__ hmax) {
     if (g->err & SGE_SORT_FATAL) return;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= ng) return;
-    keys_count_one(x, y, z, h, i, g, key, count, hmax);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    keys_count_wave(x, y, z, h, i, i < ng, g, key, count, hmax);
 }
 
-// Place particles in their cell's slot range (any order), then fix the order
-// inside each cell to ascending particle id: the rank of particle i in its
-// cell is the number of smaller ids in the same cell range.
-__device__ inline void scatter_one(const int32_t* __restrict__ key, int64_t i,
-                                   const int64_t* __restrict__ off, int32_t* __restrict__ cursor,
-                                   int32_t* __restrict__ tmp) {
-    const int32_t k = key[i];
-    const int64_t slot = off[k] + atomicAdd(&cursor[k], 1);
-    tmp[slot] = (int32_t)i;
-}
-
-__device__ inline void rankfix_one(const int32_t* __restrict__ key, int64_t s,
-                                   const int64_t* __restrict__ off,
-                                   const int32_t* __restrict__ tmp, int32_t* __restrict__ perm) {
-    const int32_t i = tmp[s];
-    const int32_t k = key[i];
-    const int64_t lo = off[k], hi = off[k + 1];
-    int64_t r = 0;
-    for (int64_t t = lo; t < hi; ++t) r += tmp[t] < i;
-    perm[lo + r] = i;
-}
-
+// The stable order of the gas by cell key (ascending particle id inside a
+// cell) comes from an LSD radix sort of the keys, sg_launch_gas_order;
+// here the gather of the sorted state.
 __device__ inline void gather_one(const int32_t* __restrict__ perm, int64_t s,
                                   const double* __restrict__ x, const double* __restrict__ y,
                                   const double* __restrict__ z, const double* __restrict__ h,
@@ -495,28 +501,6 @@ __device__ inline void gather_one(const int32_t* __restrict__ perm, int64_t s,
     hs[s] = ph;
     ms[s] = pm;
     prec[s] = sg_prec{px, py, pz, ph, pm, {0.0, 0.0, 0.0}};
-}
-
-__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ key, int64_t ng,
-                                                    const sg_grid_dev* g,
-                                                    const int64_t* __restrict__ off,
-                                                    int32_t* __restrict__ cursor,
-                                                    int32_t* __restrict__ tmp) {
-    if (g->err & SGE_SORT_FATAL) return;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= ng) return;
-    scatter_one(key, i, off, cursor, tmp);
-}
-
-__global__ __launch_bounds__(kBlock) void k_rankfix(const int32_t* __restrict__ key, int64_t ng,
-                                                    const sg_grid_dev* g,
-                                                    const int64_t* __restrict__ off,
-                                                    const int32_t* __restrict__ tmp,
-                                                    int32_t* __restrict__ perm) {
-    if (g->err & SGE_SORT_FATAL) return;
-    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= ng) return;
-    rankfix_one(key, s, off, tmp, perm);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_gas(
@@ -672,13 +656,17 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
 // digit (chunk by chunk, wave by wave, lane by lane).  Per chunk, the first
 // lane of each (wave, digit) group publishes the group's size; after the
 // writes it adds that size to the digit's running count and clears its slot.
+// vin == nullptr stands for the values 0, 1, 2, .. (the element indices).
 __device__ inline void radix_scatter_tile(const uint32_t* __restrict__ kin,
                                           const int32_t* __restrict__ vin, int64_t n, int shift,
                                           int64_t ntiles, const int64_t* __restrict__ offs,
                                           uint32_t* __restrict__ kout,
                                           int32_t* __restrict__ vout, int64_t tile) {
+    // a (wave, digit) group of one chunk has at most 64 members: one byte
+    // each keeps the workgroup's LDS at 8 KB, small enough to find room on
+    // CUs that a persistent gravity kernel mostly fills
     __shared__ int32_t s_run[kBuckets];
-    __shared__ int32_t s_w[kBlock / 64][kBuckets];
+    __shared__ uint8_t s_w[kBlock / 64][kBuckets];
     const int wave = threadIdx.x >> 6;
     for (int t = threadIdx.x; t < kBuckets; t += kBlock) {
         s_run[t] = 0;
@@ -690,7 +678,7 @@ __device__ inline void radix_scatter_tile(const uint32_t* __restrict__ kin,
         const int64_t i = base + k * kBlock + threadIdx.x;
         const bool valid = i < n;
         const uint32_t key = valid ? kin[i] : 0u;
-        const int32_t val = valid ? vin[i] : 0;
+        const int32_t val = valid ? (vin ? vin[i] : (int32_t)i) : 0;
         const uint32_t d = (key >> shift) & (kBuckets - 1);
         unsigned long long peers = __ballot(valid);
         for (int b = 0; b < kRadixBits; ++b) {
@@ -700,7 +688,7 @@ __device__ inline void radix_scatter_tile(const uint32_t* __restrict__ kin,
         const unsigned r = rank_below(peers);
         const int cnt = __builtin_popcountll(peers);
         const bool lead = valid && r == 0;
-        if (lead) s_w[wave][d] = cnt;
+        if (lead) s_w[wave][d] = (uint8_t)cnt;
         __syncthreads();
         if (valid) {
             int32_t pre = 0;
@@ -781,12 +769,18 @@ __global__ __launch_bounds__(kBlock) void k_seg_radix_scatter(const sg_seg_sys* 
 }
 
 // Exclusive scan of one system's digit histogram (1024 * ntiles counts)
-// into its offsets, one workgroup of 1024 lanes per system; offs[total] is
-// not needed by the scatter and not written.
-constexpr int kSegScanBlock = 1024;
-__global__ __launch_bounds__(kSegScanBlock) void k_seg_scan_hist(const sg_seg_sys* __restrict__ sys) {
+// into its offsets, one workgroup per system; offs[total] is not needed by
+// the scatter and not written.  gas: the cell-key sort's histogram, else the
+// Morton sort's.  256 lanes: the cell-key sort runs beside the persistent
+// gravity kernel, and a 1024-lane workgroup (4 free wave slots on every
+// SIMD of one CU) waited there for the gravity kernel to end (173 ms).
+constexpr int kSegScanBlock = 256;
+__global__ __launch_bounds__(kSegScanBlock) void k_seg_scan_hist(const sg_seg_sys* __restrict__ sys,
+                                                                 int gas) {
     const sg_seg_sys& S = sys[blockIdx.x];
-    const int64_t n = (int64_t)kBuckets * S.ntiles;
+    const int32_t* hist = gas ? S.ghist : S.mhist;
+    int64_t* offs = gas ? S.goffs : S.moffs;
+    const int64_t n = (int64_t)kBuckets * (gas ? S.gntiles : S.ntiles);
     __shared__ int64_t s_w[kSegScanBlock / 64];
     __shared__ int64_t s_carry;
     if (threadIdx.x == 0) s_carry = 0;
@@ -796,7 +790,7 @@ __global__ __launch_bounds__(kSegScanBlock) void k_seg_scan_hist(const sg_seg_sy
         const int64_t i0 = c0 + (int64_t)threadIdx.x * kItems;
         int64_t v[kItems], tsum = 0;
         for (int k = 0; k < kItems; ++k) {
-            v[k] = i0 + k < n ? S.mhist[i0 + k] : 0;
+            v[k] = i0 + k < n ? hist[i0 + k] : 0;
             tsum += v[k];
         }
         int64_t incl = tsum;
@@ -810,7 +804,7 @@ __global__ __launch_bounds__(kSegScanBlock) void k_seg_scan_hist(const sg_seg_sy
         for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += s_w[w];
         int64_t run = wbase + incl - tsum;
         for (int k = 0; k < kItems; ++k) {
-            if (i0 + k < n) S.moffs[i0 + k] = run;
+            if (i0 + k < n) offs[i0 + k] = run;
             run += v[k];
         }
         __syncthreads();
@@ -863,7 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_cells_clear(const sg_seg_sys* __
     int64_t lb;
     const int k = sg_seg_find(pfx, nsys, blockIdx.x, &lb);
     const sg_seg_sys& S = sys[k];
-    cells_clear_block(S.g, S.count, S.hmax, S.cursor, lb, pfx[k + 1] - pfx[k]);
+    cells_clear_block(S.g, S.count, S.hmax, lb, pfx[k + 1] - pfx[k]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_keys_count(const sg_seg_sys* __restrict__ sys,
@@ -873,7 +867,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_keys_count(const sg_seg_sys* __r
     const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
     if (S.g->err & SGE_SORT_FATAL) return;
     const int64_t i = lb * kBlock + threadIdx.x;
-    if (i < S.ng) keys_count_one(S.x, S.y, S.z, S.h, i, S.g, S.key, S.count, S.hmax);
+    keys_count_wave(S.x, S.y, S.z, S.h, i, i < S.ng, S.g, S.key, S.count, S.hmax);
 }
 
 // which = 0: cell counts -> cell offsets (n = M from the grid, bounded by
@@ -926,22 +920,36 @@ __global__ __launch_bounds__(kBlock) void k_seg_scan_down(const sg_seg_sys* __re
     scan_down_tile(in, out, n, tile, (const int64_t*)S.scan);
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_scatter(const sg_seg_sys* __restrict__ sys,
-                                                        const int64_t* __restrict__ pfx, int nsys) {
-    int64_t lb;
-    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
-    if (S.g->err & SGE_SORT_FATAL) return;
-    const int64_t i = lb * kBlock + threadIdx.x;
-    if (i < S.ng) scatter_one(S.key, i, S.off, S.cursor, S.tmp);
+// Cell-key radix pass `pass` of every system (the per-system buffers'
+// ping-pong of sg_launch_gas_order); the last pass writes the order.
+__device__ inline void seg_gas_bufs(const sg_seg_sys& S, int pass, const uint32_t** kin,
+                                    const int32_t** vin) {
+    *kin = pass == 0 ? (const uint32_t*)S.key : (((pass - 1) & 1) ? S.gk1 : S.gk0);
+    *vin = pass == 0 ? nullptr : (((pass - 1) & 1) ? S.gv1 : S.gv0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_rankfix(const sg_seg_sys* __restrict__ sys,
-                                                        const int64_t* __restrict__ pfx, int nsys) {
-    int64_t lb;
-    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
-    if (S.g->err & SGE_SORT_FATAL) return;
-    const int64_t s = lb * kBlock + threadIdx.x;
-    if (s < S.ng) rankfix_one(S.key, s, S.off, S.tmp, const_cast<int32_t*>(S.sph.perm));
+__global__ __launch_bounds__(kBlock) void k_seg_gas_hist(const sg_seg_sys* __restrict__ sys,
+                                                         const int64_t* __restrict__ pfx,
+                                                         int nsys, int pass) {
+    int64_t tile;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &tile)];
+    const uint32_t* kin;
+    const int32_t* vin;
+    seg_gas_bufs(S, pass, &kin, &vin);
+    radix_hist_tile(kin, S.ng, kRadixBits * pass, S.gntiles, S.ghist, tile);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_gas_scatter(const sg_seg_sys* __restrict__ sys,
+                                                            const int64_t* __restrict__ pfx,
+                                                            int nsys, int pass, int last) {
+    int64_t tile;
+    const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &tile)];
+    const uint32_t* kin;
+    const int32_t* vin;
+    seg_gas_bufs(S, pass, &kin, &vin);
+    int32_t* vout = last ? const_cast<int32_t*>(S.sph.perm) : ((pass & 1) ? S.gv1 : S.gv0);
+    radix_scatter_tile(kin, vin, S.ng, kRadixBits * pass, S.gntiles, S.goffs,
+                       (pass & 1) ? S.gk1 : S.gk0, vout, tile);
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_gather_gas(const sg_seg_sys* __restrict__ sys,
@@ -1001,10 +1009,10 @@ void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, int cell_scale_log2
 }
 
 void sg_launch_cells_clear(sg_grid_dev* g, int32_t* count, unsigned long long* hmax,
-                           int32_t* cursor, int64_t cell_cap, hipStream_t st) {
+                           int64_t cell_cap, hipStream_t st) {
     unsigned nb = grid_for(cell_cap, kBlock);
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_cells_clear, dim3(nb), dim3(kBlock), 0, st, g, count, hmax, cursor);
+    hipLaunchKernelGGL(k_cells_clear, dim3(nb), dim3(kBlock), 0, st, g, count, hmax);
 }
 
 void sg_launch_keys_count(const double* x, const double* y, const double* z, const double* h,
@@ -1012,15 +1020,6 @@ void sg_launch_keys_count(const double* x, const double* y, const double* z, con
                           unsigned long long* hmax, hipStream_t st) {
     hipLaunchKernelGGL(k_keys_count, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, st, x, y, z,
                        h, ng, g, key, count, hmax);
-}
-
-void sg_launch_scatter_rank(const int32_t* key, int64_t ng, const sg_grid_dev* g,
-                            const int64_t* off, int32_t* cursor, int32_t* tmp, int32_t* perm,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, st, key, ng, g,
-                       off, cursor, tmp);
-    hipLaunchKernelGGL(k_rankfix, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, st, key, ng, g,
-                       off, tmp, perm);
 }
 
 void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
@@ -1092,8 +1091,15 @@ void sg_seg_launch_sort(const sg_seg& s, hipStream_t st) {
                        s.sys, pcl, s.nsys);
     hipLaunchKernelGGL(k_seg_keys_count, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
     seg_scan(s, 0, st);
-    hipLaunchKernelGGL(k_seg_scatter, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
-    hipLaunchKernelGGL(k_seg_rankfix, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
+    const int64_t* pgt = s.pfx + SG_SEG_GTILES * (s.nsys + 1);
+    for (int pass = 0; pass < s.gas_passes; ++pass) {
+        hipLaunchKernelGGL(k_seg_gas_hist, dim3((unsigned)s.nblk[SG_SEG_GTILES]), dim3(kBlock), 0,
+                           st, s.sys, pgt, s.nsys, pass);
+        hipLaunchKernelGGL(k_seg_scan_hist, dim3((unsigned)s.nsys), dim3(kSegScanBlock), 0, st,
+                           s.sys, 1);
+        hipLaunchKernelGGL(k_seg_gas_scatter, dim3((unsigned)s.nblk[SG_SEG_GTILES]), dim3(kBlock),
+                           0, st, s.sys, pgt, s.nsys, pass, pass == s.gas_passes - 1 ? 1 : 0);
+    }
     hipLaunchKernelGGL(k_seg_gather_gas, dim3(nbg), dim3(kBlock), 0, st, s.sys, png, s.nsys);
 }
 
@@ -1126,9 +1132,47 @@ void sg_seg_launch_morton_order(const sg_seg& s, hipStream_t st) {
         hipLaunchKernelGGL(k_seg_radix_hist, dim3((unsigned)s.nblk[SG_SEG_TILES]), dim3(kBlock), 0,
                            st, s.sys, pt, s.nsys, pass);
         hipLaunchKernelGGL(k_seg_scan_hist, dim3((unsigned)s.nsys), dim3(kSegScanBlock), 0, st,
-                           s.sys);
+                           s.sys, 0);
         hipLaunchKernelGGL(k_seg_radix_scatter, dim3((unsigned)s.nblk[SG_SEG_TILES]), dim3(kBlock),
                            0, st, s.sys, pt, s.nsys, pass);
+    }
+}
+
+int sg_gas_radix_passes(int64_t cell_cap) {
+    uint64_t top = cell_cap > 1 ? (uint64_t)(cell_cap - 1) : 1u;   // largest key
+    int bits = 0;
+    while (top) {
+        ++bits;
+        top >>= 1;
+    }
+    return (bits + kRadixBits - 1) / kRadixBits;
+}
+
+void sg_launch_gas_order(const int32_t* key, int64_t ng, int64_t cell_cap, void* tmp,
+                         int32_t* perm, hipStream_t st) {
+    uint32_t *k0, *k1;
+    int32_t *v0, *v1, *hist;
+    int64_t* offs;
+    int64_t ntiles;
+    sg_morton_ptrs(tmp, ng, &k0, &k1, &v0, &v1, &hist, &offs, &ntiles);
+    size_t o_k1, o_v0, o_v1, o_hist, o_offs, o_scan, total;
+    morton_layout(ng, &o_k1, &o_v0, &o_v1, &o_hist, &o_offs, &o_scan, &total);
+    void* scan_tmp = (char*)tmp + o_scan;
+    uint32_t* kb[2] = {k0, k1};
+    int32_t* vb[2] = {v0, v1};
+    const int passes = sg_gas_radix_passes(cell_cap);
+    const uint32_t* kin = (const uint32_t*)key;        // keys are >= 0
+    const int32_t* vin = nullptr;                        // ids 0 .. ng-1
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = kRadixBits * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kBlock), 0, st, kin, ng,
+                           shift, ntiles, hist);
+        sg_launch_scan(hist, offs, kBuckets * ntiles, nullptr, kBuckets * ntiles, scan_tmp, st);
+        int32_t* vout = pass == passes - 1 ? perm : vb[pass & 1];
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kBlock), 0, st, kin, vin,
+                           ng, shift, ntiles, offs, kb[pass & 1], vout);
+        kin = kb[pass & 1];
+        vin = vb[pass & 1];
     }
 }
 

@@ -36,6 +36,9 @@ def main():
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--reorder", type=int, default=0,
                     help="gravity preparations per Morton-order recomputation (0 = every one)")
+    ap.add_argument("--chain-stream", choices=["cu", "torch"], default="cu",
+                    help="stream of the systems' corrector chains beside the batched gravity: "
+                         "the library's CU-masked stream or a torch stream")
     args = ap.parse_args()
     import torch
     from paper_1807_08116_amd import ic
@@ -58,7 +61,7 @@ def main():
         log("autotuned ensemble launch %s (%.1fs)" % (shape, time.perf_counter() - t))
     if args.reorder:
         shape["grav_reorder"] = args.reorder
-    ens = sg.Ensemble(states, **shape)
+    ens = sg.Ensemble(states, chain_stream=None if args.chain_stream == "cu" else "new", **shape)
     st = ens.stream
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
@@ -102,7 +105,7 @@ def main():
         "batched_speedup": ms_single / ms_batched,
         "steps": args.steps, "steps_per_s_graph": args.steps / sec[True],
         "steps_per_s_eager": args.steps / sec[False], "precision": "fp32c",
-        "grav_reorder": args.reorder or 1,
+        "grav_reorder": args.reorder or 1, "chain_stream": args.chain_stream,
         "launch": shape or "automatic",
     }
     print(json.dumps(out), flush=True)

@@ -444,7 +444,7 @@ class Ensemble:
     """Independent systems (one Engine each, FP32C, one shared stream) whose
     gravity runs as one persistent launch."""
 
-    def __init__(self, states, device="cuda", grav_stream=None, **kw):
+    def __init__(self, states, device="cuda", chain_stream=None, **kw):
         import torch
         self.torch = torch
         dev = torch.device(device)
@@ -459,12 +459,13 @@ class Ensemble:
         handles = (C.c_void_p * len(self.engines))(*[e.ctx.h.value for e in self.engines])
         h = C.c_void_p()
         torch.cuda.synchronize()
-        # grav_stream: None = the library's CU-masked stream, "new" = a torch
+        # chain_stream (the systems' corrector chains beside the batched
+        # gravity): None = the library's CU-masked stream, "new" = a torch
         # stream, or a torch stream
-        if grav_stream == "new":
-            grav_stream = torch.cuda.Stream(device=dev)
-        self.grav_stream = grav_stream
-        gs = C.c_void_p(grav_stream.cuda_stream) if grav_stream is not None else None
+        if chain_stream == "new":
+            chain_stream = torch.cuda.Stream(device=dev)
+        self.chain_stream = chain_stream
+        gs = C.c_void_p(chain_stream.cuda_stream) if chain_stream is not None else None
         rc = L.sg_ensemble_create(handles, len(self.engines), C.c_void_p(ptr), nbytes, gs,
                                   C.byref(h))
         if rc != SG_OK:

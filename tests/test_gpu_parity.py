@@ -274,8 +274,12 @@ def _random_state(rng, ng, nh, dup=0):
     return st
 
 
+# (5000, 2000, 3000): 3001 coincident gas particles in one cell, whose
+# rows hold 3000+ neighbours each (the long-row path of the search, ~9e6
+# list entries, one cell of 3001 particles in the stable sort)
 @pytest.mark.parametrize("ng,nh,dup", [(1, 0, 0), (2, 0, 0), (0, 3, 0), (1000, 777, 0),
-                                       (257, 0, 5), (3000, 1, 40), (64, 4097, 0)])
+                                       (257, 0, 5), (3000, 1, 40), (64, 4097, 0),
+                                       (5000, 2000, 3000)])
 def test_edge_sizes(sg, orc, ng, nh, dup):
     from paper_1807_08116_amd import ic
     rng = np.random.default_rng(ng * 7919 + nh)
