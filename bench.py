@@ -32,12 +32,23 @@ HBM_PEAK = 8000.0            # GB/s
 DT = 1e-3
 
 
+def radix_passes(cell_cap):
+    """10-bit radix passes of the cell keys for keys below cell_cap."""
+    return max(1, ((max(cell_cap - 1, 1)).bit_length() + 9) // 10)
+
+
 def pass_bytes(stage, precision_form, ng, nnz, ncell):
     """Algorithmic HBM bytes of one launch group of an HBM-bound stage: every
     array the stage must read or write, counted once (per gas particle, per
     neighbour pair, per cell)."""
-    if stage == "sort":        # x,y,z,h in; keys, perm; gather 40 B in, 104 B out; cells
-        return 192 * ng + 24 * ncell
+    if stage == "sort":
+        # keys: x,y,z,h in (32 B), key out (4), count and max-h atomics (12);
+        # radix passes: the first reads keys (histogram and scatter, 8 B)
+        # and writes key and id (8), each later one reads and writes both
+        # (4 + 16); gather: perm and x,y,z,h,m in (44), sorted copies and the
+        # density records out (104); cells: count, max h, offset (24)
+        p = radix_passes(8 * ng + 4096)      # the binding's default cell capacity
+        return (48 + 16 + 20 * (p - 1) + 148) * ng + 24 * ncell
     if stage == "nbr":         # own x,y,z,h; count + offset; one int32 per pair
         return 44 * ng + 4 * nnz
     if stage == "density":     # offset, record (64 B), rho out; one index per pair
@@ -166,6 +177,10 @@ def cpu_baseline(st, sample, prm):
     ref[gas] += ref_sph
     step_s = t_nbr + t_dens + 2 * t_sph + t_grav * n / len(sample)
     cores = oracle.get_threads()
+    host = {"nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "omp_threads": cores, "kdtree_workers": oracle.kdtree_workers(),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
     # one thread: density, forces and gravity of 256 of the targets (the
     # k-d tree neighbour search keeps its all-core time)
     oracle.set_threads(1)
@@ -191,6 +206,7 @@ def cpu_baseline(st, sample, prm):
                    "SPH part (neighbours %.1fs, density %.1fs, forces %.1fs x2); gravity %.1fs"
                    % (len(sample), n, n / len(sample), t_nbr, t_dens, t_sph, t_grav)),
         "extrapolated": True,
+        "host": host,
         "single_core": {"value": 1.0 / step1_s, "unit": "force-steps/s", "cores": 1,
                         "sample": ("one thread: gravity of %d of the targets (x%.0f) + "
                                    "density %.1fs + forces %.1fs x2; gravity %.1fs; the "

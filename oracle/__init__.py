@@ -247,6 +247,17 @@ def nbr_row_brute(x, y, z, h, i):
         cap = int(c)
 
 
+def kdtree_workers():
+    """Threads of the k-d tree queries: the OpenMP thread count the oracle's C
+    code uses (OMP_NUM_THREADS, else all CPUs this process may run on)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    if hasattr(os, "sched_getaffinity"):
+        return max(1, len(os.sched_getaffinity(0)))
+    return os.cpu_count() or 1
+
+
 def nbrs_kdtree(x, y, z, h, workers=None):
     """Exact rows via k-d tree candidates (radius 2 h_i (1 + 2^-10)) + C filter."""
     from scipy.spatial import cKDTree
@@ -254,7 +265,7 @@ def nbrs_kdtree(x, y, z, h, workers=None):
     x, y, z, h = _c(x), _c(y), _c(z), _c(h)
     pts = np.stack([x, y, z], axis=1)
     tree = cKDTree(pts)
-    w = workers if workers is not None else min(16, os.cpu_count() or 1)
+    w = workers if workers is not None else kdtree_workers()
     lists = tree.query_ball_point(pts, r=2.0 * h * (1.0 + 2.0 ** -10), workers=w,
                                   return_sorted=False)
     lens = np.fromiter((len(a) for a in lists), dtype=np.int64, count=n)

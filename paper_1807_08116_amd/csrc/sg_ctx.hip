@@ -183,7 +183,6 @@ struct sg_ctx {
     bool have_nbr, have_rho, have_grav, have_pot, have_sph;
     bool predicted;        // between SG_PREDICT and SG_CORRECT
     bool accel_after_predict;
-    bool beside_grav;      // launches being enqueued share the GPU with the gravity kernel
     // Morton order of the gravity kernels: valid for the bound particles,
     // and gravity preparations since it was computed
     bool have_order;
@@ -263,7 +262,6 @@ struct sg_ctx {
         b.perm = at<int32_t>(L.perm);
         b.nbr_off = at<int64_t>(L.nbr_off);
         b.nbr_idx = at<int32_t>(L.nbr_idx);
-        b.beside_grav = beside_grav ? 1 : 0;
         return b;
     }
     void invalidate_positions() {
@@ -559,11 +557,9 @@ sg_status do_step(sg_ctx* c, double dt, uint32_t flags) {
     sg_status rg = do_gravity(c, (flags & SG_POT) != 0);
     hipStream_t own = c->st;
     c->st = c->st2;
-    c->beside_grav = true;
     sg_status rs = rg != SG_OK ? rg : do_build(c);
     if (rs == SG_OK) rs = do_density(c);
     if (rs == SG_OK) rs = do_sph(c);
-    c->beside_grav = false;
     c->st = own;
     // join (also after an error, so that a capture stays whole)
     if ((hipEventRecord(c->ev_join, c->st2) != hipSuccess ||
@@ -603,7 +599,6 @@ sg_status init_ctx(sg_ctx* c, const sg_params* prm, const sg_caps* caps, const l
     c->order_age = 0;
     c->predicted = false;
     c->accel_after_predict = false;
-    c->beside_grav = false;
     c->msg[0] = 0;
     c->prof = false;
     c->open_ev = nullptr;
@@ -1129,9 +1124,8 @@ sg_status ens_launched(sg_ens* e, const char* what) {
 
 // Neighbour lists and density of every system that lacks them: one launch
 // per stage for all systems when all lack them (every corrector), else
-// system by system.  beside: the launches share the GPU with the gravity
-// kernel (no LDS reservation in the gather passes).
-sg_status ens_lists_density(sg_ens* e, bool beside) {
+// system by system.
+sg_status ens_lists_density(sg_ens* e) {
     sg_ctx* c0 = e->c[0];
     bool all_nbr = true, all_rho = true, any = false;
     for (sg_ctx* c : e->c) {
@@ -1150,7 +1144,7 @@ sg_status ens_lists_density(sg_ens* e, bool beside) {
         sg_seg_launch_nbr_finish(e->seg, e->st);
         c0->end();
         c0->begin(SG_ST_DENSITY);
-        sg_seg_launch_density(e->seg, beside ? 1 : 0, e->st);
+        sg_seg_launch_density(e->seg, e->st);
         c0->end();
         for (sg_ctx* c : e->c) {
             c->have_nbr = true;
@@ -1160,10 +1154,8 @@ sg_status ens_lists_density(sg_ens* e, bool beside) {
     }
     sg_status r;
     for (sg_ctx* c : e->c) {
-        c->beside_grav = beside;
         r = !c->have_nbr ? do_build(c) : SG_OK;
         if (r == SG_OK && !c->have_rho) r = do_density(c);
-        c->beside_grav = false;
         if (r != SG_OK) return e->fail(r, c->msg);
     }
     return SG_OK;
@@ -1182,12 +1174,12 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
         if (c->predicted) return e->fail(SG_ESTATE, "step inside a predict/correct pair");
         need_grav |= !c->have_grav || (pot && !c->have_pot);
     }
-    if ((r = ens_lists_density(e, false)) != SG_OK) return r;
+    if ((r = ens_lists_density(e)) != SG_OK) return r;
     if (need_grav && (r = ens_gravity(e, pot)) != SG_OK) return r;
     // predictor: SPH right-hand side, total acceleration, update and the
     // gravity inputs at the predicted positions, each one launch for all
     c0->begin(SG_ST_SPH);
-    sg_seg_launch_sph_state(e->seg, 0, 0, e->st);
+    sg_seg_launch_sph_state(e->seg, 0, e->st);
     c0->end();
     c0->begin(SG_ST_UPDATE);
     sg_seg_launch_combine(e->seg, e->st);
@@ -1205,11 +1197,10 @@ sg_status ens_step(sg_ens* e, double dt, uint32_t flags) {
     // gravity kernel reads only the prepared inputs), or before them with
     // step_serial (of the first context)
     auto chains = [&]() {
-        const bool beside = !c0->prm.step_serial && e->cst;
-        sg_status q = ens_lists_density(e, beside);
+        sg_status q = ens_lists_density(e);
         if (q != SG_OK) return q;
         c0->begin(SG_ST_SPH);
-        sg_seg_launch_sph_state(e->seg, 1, beside ? 1 : 0, e->st);
+        sg_seg_launch_sph_state(e->seg, 1, e->st);
         c0->end();
         for (sg_ctx* c : e->c) c->have_sph = true;
         return ens_launched(e, "SPH forces");
@@ -1337,7 +1328,6 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
         Q.gy = S.gy;
         Q.gz = S.gz;
         Q.sph = c->sph();
-        Q.sph.beside_grav = 0;
         Q.g = c->grid();
         sg_morton_ptrs(c->at<void>(c->L.morton), c->n, &Q.mk0, &Q.mk1, &Q.mv0, &Q.mv1, &Q.mhist,
                        &Q.moffs, &Q.ntiles);
@@ -1361,7 +1351,8 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
                                           gas ? sg_scan_tiles(c->caps.cell_cap) : 0,
                                           gas ? sg_scan_tiles(c->ng) : 0,
                                           (c->ng + 3) / 4,
-                                          gas ? Q.gntiles : 0};
+                                          gas ? Q.gntiles : 0,
+                                          sg_sph_blocks(c->ng)};
         if (gas && sg_gas_radix_passes(c->caps.cell_cap) > gas_passes)
             gas_passes = sg_gas_radix_passes(c->caps.cell_cap);
         for (int q = 0; q < SG_SEG_NPFX; ++q)

@@ -154,7 +154,6 @@ struct sg_sph_bufs {
     const int32_t* perm;
     const int64_t* nbr_off;
     const int32_t* nbr_idx;
-    int beside_grav;                    // 1: the launch shares the GPU with the gravity kernel
 };
 void sg_launch_density(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
                        double* rho_out, hipStream_t st);
@@ -268,10 +267,11 @@ struct sg_seg_sys {
 // particles, of 256 gas particles, radix tiles, cell-clearing blocks
 // (grid-stride, at most 256 per system), scan tiles of the cell counts and
 // of the neighbour counts, blocks of 4 gas particles (one wavefront each),
-// and radix tiles of the gas.
+// radix tiles of the gas, and blocks of the SPH density and force passes
+// (sg_sph_blocks).
 enum {
     SG_SEG_N = 0, SG_SEG_NG = 1, SG_SEG_TILES = 2, SG_SEG_CELLS = 3, SG_SEG_SCAN_C = 4,
-    SG_SEG_SCAN_G = 5, SG_SEG_NG4 = 6, SG_SEG_GTILES = 7, SG_SEG_NPFX = 8
+    SG_SEG_SCAN_G = 5, SG_SEG_NG4 = 6, SG_SEG_GTILES = 7, SG_SEG_SPH = 8, SG_SEG_NPFX = 9
 };
 struct sg_seg {
     const sg_seg_sys* sys;           // [nsys], device
@@ -302,9 +302,10 @@ void sg_seg_launch_nbr_search(const sg_seg& s, hipStream_t st);
 void sg_seg_launch_scan_nbr(const sg_seg& s, hipStream_t st);
 void sg_seg_launch_nbr_finish(const sg_seg& s, hipStream_t st);
 // Density, and the EOS records + FP32C forces on the predicted state
-// (predicted != 0: vt, et) or the current one; `beside_grav` as in sg_sph_bufs.
-void sg_seg_launch_density(const sg_seg& s, int beside_grav, hipStream_t st);
-void sg_seg_launch_sph_state(const sg_seg& s, int predicted, int beside_grav, hipStream_t st);
+// (predicted != 0: vt, et) or the current one.
+int64_t sg_sph_blocks(int64_t ng);
+void sg_seg_launch_density(const sg_seg& s, hipStream_t st);
+void sg_seg_launch_sph_state(const sg_seg& s, int predicted, hipStream_t st);
 
 // Update and diagnostics.
 void sg_launch_predict(int64_t n, int64_t ng, double dt, double* x, double* y, double* z,

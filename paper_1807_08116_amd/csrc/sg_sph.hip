@@ -6,7 +6,8 @@
 //
 // Work is done on the gas gathered into sorted-slot order, so a target's
 // neighbours are close in memory; results are scattered back to particle
-// order.  One thread per target slot walks its CSR row.
+// order.  The density and force passes walk a target's CSR row with a small
+// group of lanes; the other passes take one thread per slot.
 //
 // FP64 form: every pair quantity in FP64.  FP32C form: the FP64 coordinate
 // difference is rounded once to FP32 (cell-relative by construction: it is
@@ -19,23 +20,36 @@ namespace {
 constexpr int kBlock = 256;
 constexpr double kPi = 3.14159265358979323846;
 
-// The density and force passes gather every neighbour's record.  With the
-// default residency (8 or more workgroups per CU) the targets in flight on
-// an XCD need more neighbour records than its 4 MB L2 holds, and most
-// gathers miss.  Their launches therefore reserve LDS they do not use, so
-// that at most 2 workgroups share a CU (160 KB of LDS per CU): measured at
-// 2M particles, density 0.91 -> 0.51 ms and the force pass 1.11 -> 0.85 ms
-// (FP32C), 1.27 -> 1.08 ms (FP64); 1 or 3 workgroups per CU were slower.
-// A pass that runs beside the gravity kernel reserves nothing: the gravity
-// workgroups hold most of every CU's LDS, so an 80 KB request would keep
-// the pass off the GPU until the gravity kernel drains.
-constexpr unsigned kGatherLds = 80 * 1024;
-
-inline unsigned gather_lds(const sg_sph_bufs& b) { return b.beside_grav ? 0u : kGatherLds; }
-
 inline unsigned grid_for(int64_t n) {
     int64_t b = (n + kBlock - 1) / kBlock;
     return (unsigned)(b < 1 ? 1 : b);
+}
+
+// The density and force passes walk a target's neighbour row with
+// kSphLanes lanes (every kSphLanes-th entry each) and combine the lanes'
+// partial sums by an exchange over the group, in a fixed order, so each
+// target's result is reproducible.  Eight lanes per target put eight
+// independent record gathers in flight where one thread per target had
+// one, and a wavefront's rows end within a few entries of each other.
+// Measured at 2M particles (1M gas): density 0.51 -> 0.24 ms, the FP32C
+// force pass (with its record build) 0.84 -> 0.56 ms, FP64 1.05 -> 0.66 ms
+// (16 lanes: no faster; an LDS reservation that caps the workgroups per
+// CU, which helped one thread per target, no longer does).  Workgroup b
+// takes slots b * kSphTargets onward, whichever XCD runs it (handing each
+// XCD a contiguous share of the slots measured slightly slower).
+constexpr int kSphLanes = 8;
+constexpr int kSphTargets = kBlock / kSphLanes;     // targets per workgroup
+
+inline unsigned grid_sph(int64_t ng) {
+    int64_t b = (ng + kSphTargets - 1) / kSphTargets;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+// Sum of v over the kSphLanes lanes of this lane's group (butterfly; every
+// lane of the group gets the same value).  All lanes of the wavefront call it.
+__device__ inline double group_sum(double v) {
+    for (int o = 1; o < kSphLanes; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 struct kahan {
@@ -57,51 +71,69 @@ __device__ inline T spline_shape(T xi) {
     return t > T(0) ? T(0.25) * t * t * t : T(0);
 }
 
+// Density of target s from lane `sub` of its group; `valid` false for the
+// groups past the end (they still take part in the group exchange).
+__device__ inline void density_f64_lanes(const sg_sph_bufs& b, int64_t s, bool valid, int sub,
+                                         double* __restrict__ rho_out) {
+    double acc = 0.0;
+    sg_prec pi{};
+    if (valid) {
+        pi = b.prec[s];
+        if (sub == 0) acc = pi.m / (kPi * pi.h * pi.h * pi.h);   // self term m_i W(0, h_i)
+        const int64_t e1 = b.nbr_off[s + 1];
+        for (int64_t e = b.nbr_off[s] + sub; e < e1; e += kSphLanes) {
+            const sg_prec pj = b.prec[b.nbr_idx[e]];
+            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double hij = 0.5 * (pi.h + pj.h);
+            const double inv = 1.0 / hij;
+            acc += pj.m * spline_shape(r * inv) * (inv * inv * inv) * (1.0 / kPi);
+        }
+    }
+    acc = group_sum(acc);
+    if (valid && sub == 0) {
+        b.rho_s[s] = acc;
+        rho_out[b.perm[s]] = acc;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_density_f64(sg_sph_bufs b, const sg_grid_dev* g,
                                                         int64_t ng, double* __restrict__ rho_out) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (s >= ng) return;
-    const sg_prec pi = b.prec[s];
-    double acc = pi.m / (kPi * pi.h * pi.h * pi.h);      // self term m_i W(0, h_i)
-    const int64_t e1 = b.nbr_off[s + 1];
-    for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
-        const sg_prec pj = b.prec[b.nbr_idx[e]];
-        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-        const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        const double hij = 0.5 * (pi.h + pj.h);
-        const double inv = 1.0 / hij;
-        acc += pj.m * spline_shape(r * inv) * (inv * inv * inv) * (1.0 / kPi);
-    }
-    b.rho_s[s] = acc;
-    rho_out[b.perm[s]] = acc;
+    const int64_t s = (int64_t)blockIdx.x * kSphTargets + threadIdx.x / kSphLanes;
+    density_f64_lanes(b, s, s < ng, threadIdx.x % kSphLanes, rho_out);
 }
 
-__device__ inline void density_f32_one(const sg_sph_bufs& b, int64_t s,
-                                       double* __restrict__ rho_out) {
-    const sg_prec pi = b.prec[s];
-    const float hi = (float)pi.h;
-    kahan acc{(float)(pi.m / (kPi * pi.h * pi.h * pi.h)), 0.0f};
-    const int64_t e1 = b.nbr_off[s + 1];
-    for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
-        const sg_prec pj = b.prec[b.nbr_idx[e]];
-        const float dx = (float)(pi.x - pj.x), dy = (float)(pi.y - pj.y), dz = (float)(pi.z - pj.z);
-        const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-        const float hij = 0.5f * (hi + (float)pj.h);
-        const float inv = 1.0f / hij;
-        acc.add((float)pj.m * spline_shape(r * inv) * (inv * inv * inv) * (float)(1.0 / kPi));
+__device__ inline void density_f32_lanes(const sg_sph_bufs& b, int64_t s, bool valid, int sub,
+                                         double* __restrict__ rho_out) {
+    kahan acc{0.0f, 0.0f};
+    if (valid) {
+        const sg_prec pi = b.prec[s];
+        const float hi = (float)pi.h;
+        if (sub == 0) acc.s = (float)(pi.m / (kPi * pi.h * pi.h * pi.h));
+        const int64_t e1 = b.nbr_off[s + 1];
+        for (int64_t e = b.nbr_off[s] + sub; e < e1; e += kSphLanes) {
+            const sg_prec pj = b.prec[b.nbr_idx[e]];
+            const float dx = (float)(pi.x - pj.x), dy = (float)(pi.y - pj.y),
+                        dz = (float)(pi.z - pj.z);
+            const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+            const float hij = 0.5f * (hi + (float)pj.h);
+            const float inv = 1.0f / hij;
+            acc.add((float)pj.m * spline_shape(r * inv) * (inv * inv * inv) * (float)(1.0 / kPi));
+        }
     }
-    const double rho = acc.value();
-    b.rho_s[s] = rho;
-    rho_out[b.perm[s]] = rho;
+    const double rho = group_sum(acc.value());
+    if (valid && sub == 0) {
+        b.rho_s[s] = rho;
+        rho_out[b.perm[s]] = rho;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_density_f32(sg_sph_bufs b, const sg_grid_dev* g,
                                                         int64_t ng, double* __restrict__ rho_out) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (s >= ng) return;
-    density_f32_one(b, s, rho_out);
+    const int64_t s = (int64_t)blockIdx.x * kSphTargets + threadIdx.x / kSphLanes;
+    density_f32_lanes(b, s, s < ng, threadIdx.x % kSphLanes, rho_out);
 }
 
 // Pack the state the force pass should use (velocities and energies of the
@@ -150,6 +182,56 @@ __global__ __launch_bounds__(kBlock) void k_sph_prep(sg_sph_bufs b, const sg_gri
     sph_prep_one(b, s, precision, gamma, vx, vy, vz, e);
 }
 
+__device__ inline void sph_force_f64_lanes(const sg_sph_bufs& b, int64_t s, bool valid, int sub,
+                                           double alpha, double beta, double eta,
+                                           double* __restrict__ asx, double* __restrict__ asy,
+                                           double* __restrict__ asz, double* __restrict__ dedt) {
+    const double kgrad = -45.0 / (64.0 * kPi);
+    double sx = 0, sy = 0, sz = 0, se = 0;
+    if (valid) {
+        const sg_frec64 a = b.f64[s];
+        const int64_t e1 = b.nbr_off[s + 1];
+        for (int64_t e = b.nbr_off[s] + sub; e < e1; e += kSphLanes) {
+            const sg_frec64 o = b.f64[b.nbr_idx[e]];
+            const double dx = a.x - o.x, dy = a.y - o.y, dz = a.z - o.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;                       // coincident pair: no gradient
+            const double r = sqrt(r2);
+            const double hij = 0.5 * (a.h + o.h);
+            const double inv = 1.0 / hij;
+            const double q = 2.0 - r * inv;
+            if (q <= 0.0) continue;
+            const double dvx = a.vx - o.vx, dvy = a.vy - o.vy, dvz = a.vz - o.vz;
+            const double rv = dx * dvx + dy * dvy + dz * dvz;
+            double nu = 0.0;
+            if (rv < 0.0) {
+                const double mu = hij * rv / (r2 + eta * hij * hij);
+                nu = mu * (beta * mu - alpha * 0.5 * (a.c + o.c)) / (0.5 * (a.rho + o.rho));
+            }
+            const double Pij = a.P + o.P + nu;
+            // grad W_p = dW_p/dxi * r_ij / (|r_ij| h_ij) = gw * r_ij
+            const double inv2 = inv * inv;
+            const double gw = kgrad * q * q * (inv2 * inv2) / r;
+            const double f = o.m * Pij * gw;
+            sx -= f * dx;
+            sy -= f * dy;
+            sz -= f * dz;
+            se += f * rv;
+        }
+    }
+    sx = group_sum(sx);
+    sy = group_sum(sy);
+    sz = group_sum(sz);
+    se = group_sum(se);
+    if (valid && sub == 0) {
+        const int32_t i = b.perm[s];
+        asx[i] = sx;
+        asy[i] = sy;
+        asz[i] = sz;
+        dedt[i] = 0.5 * se;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_sph_force_f64(sg_sph_bufs b, const sg_grid_dev* g,
                                                           int64_t ng, double alpha, double beta,
                                                           double eta, double* __restrict__ asx,
@@ -157,85 +239,59 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f64(sg_sph_bufs b, const s
                                                           double* __restrict__ asz,
                                                           double* __restrict__ dedt) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (s >= ng) return;
-    const sg_frec64 a = b.f64[s];
-    const double kgrad = -45.0 / (64.0 * kPi);
-    double sx = 0, sy = 0, sz = 0, se = 0;
-    const int64_t e1 = b.nbr_off[s + 1];
-    for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
-        const sg_frec64 o = b.f64[b.nbr_idx[e]];
-        const double dx = a.x - o.x, dy = a.y - o.y, dz = a.z - o.z;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 == 0.0) continue;                       // coincident pair: no gradient
-        const double r = sqrt(r2);
-        const double hij = 0.5 * (a.h + o.h);
-        const double inv = 1.0 / hij;
-        const double q = 2.0 - r * inv;
-        if (q <= 0.0) continue;
-        const double dvx = a.vx - o.vx, dvy = a.vy - o.vy, dvz = a.vz - o.vz;
-        const double rv = dx * dvx + dy * dvy + dz * dvz;
-        double nu = 0.0;
-        if (rv < 0.0) {
-            const double mu = hij * rv / (r2 + eta * hij * hij);
-            nu = mu * (beta * mu - alpha * 0.5 * (a.c + o.c)) / (0.5 * (a.rho + o.rho));
-        }
-        const double Pij = a.P + o.P + nu;
-        // grad W_p = dW_p/dxi * r_ij / (|r_ij| h_ij) = gw * r_ij
-        const double inv2 = inv * inv;
-        const double gw = kgrad * q * q * (inv2 * inv2) / r;
-        const double f = o.m * Pij * gw;
-        sx -= f * dx;
-        sy -= f * dy;
-        sz -= f * dz;
-        se += f * rv;
-    }
-    const int32_t i = b.perm[s];
-    asx[i] = sx;
-    asy[i] = sy;
-    asz[i] = sz;
-    dedt[i] = 0.5 * se;
+    const int64_t s = (int64_t)blockIdx.x * kSphTargets + threadIdx.x / kSphLanes;
+    sph_force_f64_lanes(b, s, s < ng, threadIdx.x % kSphLanes, alpha, beta, eta, asx, asy, asz,
+                        dedt);
 }
 
-__device__ inline void sph_force_f32_one(const sg_sph_bufs& b, int64_t s, float alpha,
-                                         float beta, float eta, double* __restrict__ asx,
-                                         double* __restrict__ asy, double* __restrict__ asz,
-                                         double* __restrict__ dedt) {
-    const sg_frec32 a = b.f32[s];
+__device__ inline void sph_force_f32_lanes(const sg_sph_bufs& b, int64_t s, bool valid, int sub,
+                                           float alpha, float beta, float eta,
+                                           double* __restrict__ asx, double* __restrict__ asy,
+                                           double* __restrict__ asz, double* __restrict__ dedt) {
     const float kgrad = (float)(-45.0 / (64.0 * kPi));
     kahan sx{0, 0}, sy{0, 0}, sz{0, 0}, se{0, 0};
-    const int64_t e1 = b.nbr_off[s + 1];
-    for (int64_t e = b.nbr_off[s]; e < e1; ++e) {
-        const sg_frec32 o = b.f32[b.nbr_idx[e]];
-        const float dx = (float)(a.x - o.x), dy = (float)(a.y - o.y), dz = (float)(a.z - o.z);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 == 0.0f) continue;
-        const float r = sqrtf(r2);
-        const float hij = 0.5f * (a.h + o.h);
-        const float inv = 1.0f / hij;
-        const float q = 2.0f - r * inv;
-        if (q <= 0.0f) continue;
-        const float dvx = a.vx - o.vx, dvy = a.vy - o.vy, dvz = a.vz - o.vz;
-        const float rv = dx * dvx + dy * dvy + dz * dvz;
-        float nu = 0.0f;
-        if (rv < 0.0f) {
-            const float mu = hij * rv / (r2 + eta * hij * hij);
-            nu = mu * (beta * mu - alpha * 0.5f * (a.c + o.c)) / (0.5f * (a.rho + o.rho));
+    if (valid) {
+        const sg_frec32 a = b.f32[s];
+        const int64_t e1 = b.nbr_off[s + 1];
+        for (int64_t e = b.nbr_off[s] + sub; e < e1; e += kSphLanes) {
+            const sg_frec32 o = b.f32[b.nbr_idx[e]];
+            const float dx = (float)(a.x - o.x), dy = (float)(a.y - o.y),
+                        dz = (float)(a.z - o.z);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0f) continue;
+            const float r = sqrtf(r2);
+            const float hij = 0.5f * (a.h + o.h);
+            const float inv = 1.0f / hij;
+            const float q = 2.0f - r * inv;
+            if (q <= 0.0f) continue;
+            const float dvx = a.vx - o.vx, dvy = a.vy - o.vy, dvz = a.vz - o.vz;
+            const float rv = dx * dvx + dy * dvy + dz * dvz;
+            float nu = 0.0f;
+            if (rv < 0.0f) {
+                const float mu = hij * rv / (r2 + eta * hij * hij);
+                nu = mu * (beta * mu - alpha * 0.5f * (a.c + o.c)) / (0.5f * (a.rho + o.rho));
+            }
+            const float Pij = a.P + o.P + nu;
+            const float inv2 = inv * inv;
+            const float gw = kgrad * q * q * (inv2 * inv2) / r;
+            const float f = o.m * Pij * gw;
+            sx.add(-f * dx);
+            sy.add(-f * dy);
+            sz.add(-f * dz);
+            se.add(f * rv);
         }
-        const float Pij = a.P + o.P + nu;
-        const float inv2 = inv * inv;
-        const float gw = kgrad * q * q * (inv2 * inv2) / r;
-        const float f = o.m * Pij * gw;
-        sx.add(-f * dx);
-        sy.add(-f * dy);
-        sz.add(-f * dz);
-        se.add(f * rv);
     }
-    const int32_t i = b.perm[s];
-    asx[i] = sx.value();
-    asy[i] = sy.value();
-    asz[i] = sz.value();
-    dedt[i] = 0.5 * se.value();
+    // each lane's compensated sum is exact to FP32 rounding of its terms;
+    // the group combines them in FP64
+    const double vx = group_sum(sx.value()), vy = group_sum(sy.value());
+    const double vz = group_sum(sz.value()), ve = group_sum(se.value());
+    if (valid && sub == 0) {
+        const int32_t i = b.perm[s];
+        asx[i] = vx;
+        asy[i] = vy;
+        asz[i] = vz;
+        dedt[i] = 0.5 * ve;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const sg_grid_dev* g,
@@ -245,13 +301,14 @@ __global__ __launch_bounds__(kBlock) void k_sph_force_f32(sg_sph_bufs b, const s
                                                           double* __restrict__ asz,
                                                           double* __restrict__ dedt) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (s >= ng) return;
-    sph_force_f32_one(b, s, alpha, beta, eta, asx, asy, asz, dedt);
+    const int64_t s = (int64_t)blockIdx.x * kSphTargets + threadIdx.x / kSphLanes;
+    sph_force_f32_lanes(b, s, s < ng, threadIdx.x % kSphLanes, alpha, beta, eta, asx, asy, asz,
+                        dedt);
 }
 
 // Density, EOS records and the FP32C force pass for every system of an
-// ensemble (blocks of 256 gas slots per system); the records take the
+// ensemble (the density and force passes take blocks of kSphTargets gas
+// slots per system, the records blocks of 256); the records take the
 // current state, or the predicted one (predicted != 0).
 __global__ __launch_bounds__(kBlock) void k_seg_density(const sg_seg_sys* __restrict__ sys,
                                                         const int64_t* __restrict__ pfx,
@@ -259,9 +316,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_density(const sg_seg_sys* __rest
     int64_t lb;
     const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
     if (S.g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = lb * kBlock + threadIdx.x;
-    if (s >= S.ng) return;
-    density_f32_one(S.sph, s, S.rho);
+    const int64_t s = lb * kSphTargets + threadIdx.x / kSphLanes;
+    density_f32_lanes(S.sph, s, s < S.ng, threadIdx.x % kSphLanes, S.rho);
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_sph_prep(const sg_seg_sys* __restrict__ sys,
@@ -282,10 +338,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_sph_force(const sg_seg_sys* __re
     int64_t lb;
     const sg_seg_sys& S = sys[sg_seg_find(pfx, nsys, blockIdx.x, &lb)];
     if (S.g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
-    const int64_t s = lb * kBlock + threadIdx.x;
-    if (s >= S.ng) return;
-    sph_force_f32_one(S.sph, s, (float)S.alpha, (float)S.beta, (float)S.eta, S.asx, S.asy, S.asz,
-                      S.dedt);
+    const int64_t s = lb * kSphTargets + threadIdx.x / kSphLanes;
+    sph_force_f32_lanes(S.sph, s, s < S.ng, threadIdx.x % kSphLanes, (float)S.alpha,
+                        (float)S.beta, (float)S.eta, S.asx, S.asy, S.asz, S.dedt);
 }
 
 // Step control of Sec. 2.2.  CFL bound of Eq. (dt-stability) per gas slot,
@@ -360,9 +415,9 @@ __global__ __launch_bounds__(kBlock) void k_update_h(sg_sph_bufs b, const sg_gri
 void sg_launch_density(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
                        double* rho_out, hipStream_t st) {
     if (precision == SG_FP32C)
-        hipLaunchKernelGGL(k_density_f32, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng, rho_out);
+        hipLaunchKernelGGL(k_density_f32, dim3(grid_sph(ng)), dim3(kBlock), 0, st, b, g, ng, rho_out);
     else
-        hipLaunchKernelGGL(k_density_f64, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng, rho_out);
+        hipLaunchKernelGGL(k_density_f64, dim3(grid_sph(ng)), dim3(kBlock), 0, st, b, g, ng, rho_out);
 }
 
 void sg_launch_sph_prep(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
@@ -376,27 +431,29 @@ void sg_launch_sph_force(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng,
                          double alpha, double beta, double eta, double* asx, double* asy,
                          double* asz, double* dedt, hipStream_t st) {
     if (precision == SG_FP32C)
-        hipLaunchKernelGGL(k_sph_force_f32, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng,
+        hipLaunchKernelGGL(k_sph_force_f32, dim3(grid_sph(ng)), dim3(kBlock), 0, st, b, g, ng,
                            (float)alpha, (float)beta, (float)eta, asx, asy, asz, dedt);
     else
-        hipLaunchKernelGGL(k_sph_force_f64, dim3(grid_for(ng)), dim3(kBlock), gather_lds(b), st, b, g, ng,
+        hipLaunchKernelGGL(k_sph_force_f64, dim3(grid_sph(ng)), dim3(kBlock), 0, st, b, g, ng,
                            alpha, beta, eta, asx, asy, asz, dedt);
 }
 
-void sg_seg_launch_density(const sg_seg& s, int beside_grav, hipStream_t st) {
-    if (s.nblk[SG_SEG_NG] == 0) return;
-    hipLaunchKernelGGL(k_seg_density, dim3((unsigned)s.nblk[SG_SEG_NG]), dim3(kBlock),
-                       beside_grav ? 0u : kGatherLds, st, s.sys, s.pfx + SG_SEG_NG * (s.nsys + 1),
-                       s.nsys);
+int64_t sg_sph_blocks(int64_t ng) { return (ng + kSphTargets - 1) / kSphTargets; }
+
+void sg_seg_launch_density(const sg_seg& s, hipStream_t st) {
+    if (s.nblk[SG_SEG_SPH] == 0) return;
+    hipLaunchKernelGGL(k_seg_density, dim3((unsigned)s.nblk[SG_SEG_SPH]), dim3(kBlock), 0, st,
+                       s.sys,
+                       s.pfx + SG_SEG_SPH * (s.nsys + 1), s.nsys);
 }
 
-void sg_seg_launch_sph_state(const sg_seg& s, int predicted, int beside_grav, hipStream_t st) {
+void sg_seg_launch_sph_state(const sg_seg& s, int predicted, hipStream_t st) {
     if (s.nblk[SG_SEG_NG] == 0) return;
-    const int64_t* p = s.pfx + SG_SEG_NG * (s.nsys + 1);
     hipLaunchKernelGGL(k_seg_sph_prep, dim3((unsigned)s.nblk[SG_SEG_NG]), dim3(kBlock), 0, st,
-                       s.sys, p, s.nsys, predicted);
-    hipLaunchKernelGGL(k_seg_sph_force, dim3((unsigned)s.nblk[SG_SEG_NG]), dim3(kBlock),
-                       beside_grav ? 0u : kGatherLds, st, s.sys, p, s.nsys);
+                       s.sys, s.pfx + SG_SEG_NG * (s.nsys + 1), s.nsys, predicted);
+    hipLaunchKernelGGL(k_seg_sph_force, dim3((unsigned)s.nblk[SG_SEG_SPH]), dim3(kBlock), 0, st,
+                       s.sys,
+                       s.pfx + SG_SEG_SPH * (s.nsys + 1), s.nsys);
 }
 
 void sg_launch_cfl(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, double alpha,

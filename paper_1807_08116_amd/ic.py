@@ -46,12 +46,21 @@ def plummer(n, a, mass, rng, trunc=5.0):
     return pos, m
 
 
+def _workers():
+    """OMP_NUM_THREADS when set (the CPU share of the process), else the CPUs
+    this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return max(1, len(os.sched_getaffinity(0))) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
 def smoothing_lengths(pos, nmin=32, nmax=64, workers=None):
     """Bisection on h_i until #{j != i : |r_ij| < 2 h_i} lies in [nmin, nmax]."""
     from scipy.spatial import cKDTree
     n = len(pos)
     k = min(nmax + 2, n)                      # self + up to nmax + 1 others
-    w = workers if workers is not None else min(16, os.cpu_count() or 1)
+    w = workers if workers is not None else _workers()
     d, _ = cKDTree(pos).query(pos, k=k, workers=w)
     d = d[:, 1:]                              # drop self
     lo = np.zeros(n)

@@ -9,6 +9,8 @@ FP32-compensated and FP64 trajectories.
 
 Usage: python -m paper_1807_08116_amd.multistep [--config c3] [--steps 50]
            [--chunk 10] [--forms fp32c,fp64] [--dt 1e-3] [--scale 1.0]
+           [--save-hist DIR]
+       python -m paper_1807_08116_amd.multistep --compare FP32C.npy FP64.npy
 """
 import argparse
 import json
@@ -65,7 +67,17 @@ def main():
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--forms", default="fp32c,fp64")
+    ap.add_argument("--save-hist", default=None,
+                    help="directory to write each form's per-step conserved sums "
+                         "(hist_<form>_<config>.npy, rows E_kin, E_int, E_pot, E, P, L)")
+    ap.add_argument("--compare", nargs=2, default=None, metavar=("FP32C_NPY", "FP64_NPY"),
+                    help="compare two saved histories (no GPU work) and print the gaps")
     args = ap.parse_args()
+    if args.compare:
+        a, b = (np.load(f) for f in args.compare)
+        k = min(len(a), len(b))
+        print(json.dumps({"steps_compared": k - 1, **gaps(a[:k], b[:k])}), flush=True)
+        return
     from paper_1807_08116_amd import ic
     from paper_1807_08116_amd import sphgrav as sg
     sg.lib()
@@ -93,14 +105,27 @@ def main():
             "momentum_drift_max": float(dP.max()), "angmom_change_max": float(dL.max()),
             "E0": float(E0), "E_final": float(H[-1, 3]),
         }
+    if args.save_hist:
+        import os
+        os.makedirs(args.save_hist, exist_ok=True)
+        for form, H in hists.items():
+            np.save(os.path.join(args.save_hist, "hist_%s_%s.npy" % (form, args.config)), H)
     if "fp32c" in hists and "fp64" in hists:
         a, b = hists["fp32c"], hists["fp64"]
         k = min(len(a), len(b))
-        out["fp32c_vs_fp64"] = {
-            "energy_gap_max": float(np.max(np.abs(a[:k, 3] - b[:k, 3]) / abs(b[0, 3]))),
-            "momentum_gap_max": float(np.max(np.linalg.norm(a[:k, 4:7] - b[:k, 4:7], axis=1)) / pscale),
-        }
+        out["fp32c_vs_fp64"] = gaps(a[:k], b[:k])
     print(json.dumps(out), flush=True)
+
+
+def gaps(a, b):
+    """Largest gaps between two histories of the conserved sums (same steps):
+    total energy relative to |E(0)| of the second, momentum and angular
+    momentum absolute."""
+    return {
+        "energy_gap_max": float(np.max(np.abs(a[:, 3] - b[:, 3]) / abs(b[0, 3]))),
+        "momentum_gap_max": float(np.max(np.linalg.norm(a[:, 4:7] - b[:, 4:7], axis=1))),
+        "angmom_gap_max": float(np.max(np.linalg.norm(a[:, 7:10] - b[:, 7:10], axis=1))),
+    }
 
 
 if __name__ == "__main__":
