@@ -1350,9 +1350,10 @@ sg_status sg_ensemble_create(sg_ctx* const* ctxs, int32_t nsys, void* d_ws, size
                                           gas ? sg_cells_clear_blocks(c->caps.cell_cap) : 0,
                                           gas ? sg_scan_tiles(c->caps.cell_cap) : 0,
                                           gas ? sg_scan_tiles(c->ng) : 0,
-                                          (c->ng + 3) / 4,
+                                          sg_compact_blocks(c->ng),
                                           gas ? Q.gntiles : 0,
-                                          sg_sph_blocks(c->ng)};
+                                          sg_sph_blocks(c->ng),
+                                          sg_nbr_blocks(c->ng)};
         if (gas && sg_gas_radix_passes(c->caps.cell_cap) > gas_passes)
             gas_passes = sg_gas_radix_passes(c->caps.cell_cap);
         for (int q = 0; q < SG_SEG_NPFX; ++q)

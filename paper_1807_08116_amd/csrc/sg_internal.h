@@ -37,6 +37,17 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// Chunked variant: chunks of G consecutive logical blocks are dealt to the
+// XCDs in turn, so every XCD takes work from all parts of the range while
+// the blocks of one chunk share an L2.  Blocks in the tail (the last
+// nb mod 8G) keep their own index.  A bijection of [0, nb).
+__device__ inline int64_t xcd_chunk_block(int64_t b, int64_t nb, int64_t G) {
+    const int64_t span = kXcds * G;
+    if (b >= nb / span * span) return b;
+    const int64_t x = b % kXcds, k = b / kXcds;
+    return ((k / G) * kXcds + x) * G + k % G;
+}
+
 // System of block b of a segmented launch: the largest s with p[s] <= b
 // (p = per-system prefix of block counts, p[0] = 0; systems without blocks
 // are never found); *local = b - p[s].
@@ -266,12 +277,13 @@ struct sg_seg_sys {
 // Block prefixes of a segmented launch, per system: blocks of 256
 // particles, of 256 gas particles, radix tiles, cell-clearing blocks
 // (grid-stride, at most 256 per system), scan tiles of the cell counts and
-// of the neighbour counts, blocks of 4 gas particles (one wavefront each),
-// radix tiles of the gas, and blocks of the SPH density and force passes
-// (sg_sph_blocks).
+// of the neighbour counts, blocks of the list copy (sg_compact_blocks),
+// radix tiles of the gas, blocks of the SPH density and force passes
+// (sg_sph_blocks) and of the neighbour search (sg_nbr_blocks).
 enum {
     SG_SEG_N = 0, SG_SEG_NG = 1, SG_SEG_TILES = 2, SG_SEG_CELLS = 3, SG_SEG_SCAN_C = 4,
-    SG_SEG_SCAN_G = 5, SG_SEG_NG4 = 6, SG_SEG_GTILES = 7, SG_SEG_SPH = 8, SG_SEG_NPFX = 9
+    SG_SEG_SCAN_G = 5, SG_SEG_CPT = 6, SG_SEG_GTILES = 7, SG_SEG_SPH = 8, SG_SEG_NBR = 9,
+    SG_SEG_NPFX = 10
 };
 struct sg_seg {
     const sg_seg_sys* sys;           // [nsys], device
@@ -304,6 +316,8 @@ void sg_seg_launch_nbr_finish(const sg_seg& s, hipStream_t st);
 // Density, and the EOS records + FP32C forces on the predicted state
 // (predicted != 0: vt, et) or the current one.
 int64_t sg_sph_blocks(int64_t ng);
+int64_t sg_nbr_blocks(int64_t ng);
+int64_t sg_compact_blocks(int64_t ng);
 void sg_seg_launch_density(const sg_seg& s, hipStream_t st);
 void sg_seg_launch_sph_state(const sg_seg& s, int predicted, hipStream_t st);
 

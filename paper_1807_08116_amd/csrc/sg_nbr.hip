@@ -10,7 +10,7 @@
 // contiguous slot range, and visiting levels, then z, y, x in ascending
 // order yields candidates in ascending slot order: rows need no sort.
 //
-// Cell-staged search (k_nbr_search).  One wavefront takes 64 consecutive
+// Cell-staged search (k_nbr_search).  One wavefront takes 32 consecutive
 // target slots and walks them cell by cell: the targets that share a cell
 // key form a run, and the run's search region is the union (per level) of
 // its targets' boxes.  The rows of that region are flattened into one
@@ -35,6 +35,18 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+// Targets per wavefront of the search (lanes 0 .. kTargets-1 hold them;
+// all 64 lanes hold candidates).  The wavefronts' work varies widely (runs
+// of 1 to 64 targets, union boxes over 1 to 5 levels), and a resident
+// wavefront issues about one instruction in 18 cycles, so the launch is
+// bound by how well the wavefronts pack the SIMDs: at 2M particles the
+// search stage took 1.62 ms with 64 targets per wavefront, 1.53 ms with 32
+// and 1.57 ms with 16 (each run cut at a wavefront boundary repeats its
+// boxes' setup and candidate loads).
+constexpr int kTargets = 32;
+#ifndef SG_NBR_PAIR
+#define SG_NBR_PAIR 0
+#endif
 
 __device__ inline unsigned rank_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
@@ -172,7 +184,7 @@ __device__ inline float lane_f32(float v, int L) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), L));
 }
 
-// The search of wavefront w (target slots 64 w .. 64 w + 63); w is uniform.
+// The search of wavefront w (target slots kTargets w onward); w is uniform.
 __device__ __attribute__((always_inline)) inline void nbr_search_wave(
     const sg_grid_dev* __restrict__ g, int64_t ng, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ hs,
@@ -181,10 +193,10 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
     int32_t w) {
     if (g->err & SGE_SORT_FATAL) return;
     const unsigned lane = threadIdx.x & 63;
-    const int64_t g0 = (int64_t)w * 64;
+    const int64_t g0 = (int64_t)w * kTargets;
     if (g0 >= ng) return;
     const int64_t s = g0 + lane;
-    const bool live = s < ng;
+    const bool live = lane < (unsigned)kTargets && s < ng;
     double p[3] = {0.0, 0.0, 0.0}, h = 0.0;
     int32_t k = -1;
     if (live) {
@@ -256,7 +268,6 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                     const int32_t q = cb + (int32_t)lane;
                     const bool valid = q < total;
                     const int64_t t = locate(q);
-                    const int32_t trel = (int32_t)(t - g0);      // |t - g0| < ng
                     double xj = 0.0, yj = 0.0, zj = 0.0;
                     float hjf = 0.f;
                     if (valid) {
@@ -265,7 +276,41 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                         zj = zs[t];
                         hjf = (float)hs[t];
                     }
+                    const int32_t trel = (int32_t)(t - g0);      // |t - g0| < ng
                     // every target of the run against these 64 candidates
+#if SG_NBR_PAIR
+                    // two targets per pass: their tests are independent
+                    for (unsigned long long tr = run; tr;) {
+                        const int La = __builtin_ctzll(tr);
+                        tr &= tr - 1;
+                        const bool two = tr != 0;
+                        const int Lb = two ? __builtin_ctzll(tr) : La;
+                        if (two) tr &= tr - 1;
+                        const double xa = lane_f64(p[0], La), ya = lane_f64(p[1], La);
+                        const double za = lane_f64(p[2], La);
+                        const float ha = lane_f32(hif, La);
+                        const double xb = lane_f64(p[0], Lb), yb = lane_f64(p[1], Lb);
+                        const double zb = lane_f64(p[2], Lb);
+                        const float hb = lane_f32(hif, Lb);
+                        const bool oka = nbr_pred_f(xa, ya, za, ha, xj, yj, zj, hjf) & valid &
+                                         (trel != La);
+                        const bool okb = nbr_pred_f(xb, yb, zb, hb, xj, yj, zj, hjf) & valid &
+                                         (trel != Lb) & two;
+                        const unsigned long long ma = __ballot(oka), mb = __ballot(okb);
+                        if (ma) {
+                            const int32_t c0 = __builtin_amdgcn_readlane(mine, La);
+                            const int32_t pos = c0 + (int32_t)rank_below(ma);
+                            if (oka && pos < kSlot) slots[(g0 + La) * kSlot + pos] = (int32_t)t;
+                            if (lane == (unsigned)La) mine = c0 + __builtin_popcountll(ma);
+                        }
+                        if (mb) {
+                            const int32_t c0 = __builtin_amdgcn_readlane(mine, Lb);
+                            const int32_t pos = c0 + (int32_t)rank_below(mb);
+                            if (okb && pos < kSlot) slots[(g0 + Lb) * kSlot + pos] = (int32_t)t;
+                            if (lane == (unsigned)Lb) mine = c0 + __builtin_popcountll(mb);
+                        }
+                    }
+#else
                     for (unsigned long long tr = run; tr; tr &= tr - 1) {
                         const int L = __builtin_ctzll(tr);
                         const int64_t sL = g0 + L;
@@ -285,6 +330,7 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                             if (lane == (unsigned)L) mine = c0 + __builtin_popcountll(mask);
                         }
                     }
+#endif
                 }
             }
         }
@@ -298,38 +344,53 @@ __global__ __launch_bounds__(kBlock) void k_nbr_search(
     const int64_t* __restrict__ off, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ key, int32_t* __restrict__ cnt, int32_t* __restrict__ slots) {
     // first target slot of this wavefront (uniform: held in a scalar
-    // register).  Consecutive workgroups take consecutive slots whichever
-    // XCD runs them: the work per slot varies across the collision, and
-    // handing each XCD a contiguous share of the slots left some XCDs
-    // busy after the others had drained (stage 1.83 -> 1.64 ms at 1M gas).
+    // register).  The XCDs take chunks of 16 consecutive workgroups in
+    // turn: the work per slot varies across the collision, and handing
+    // each XCD one contiguous share of the slots left some XCDs busy after
+    // the others had drained (stage 1.83 -> 1.64 ms at 1M gas), while
+    // plain launch order spreads neighbouring targets over all 8 L2s
+    // (1.5x the fetched bytes of chunks of 16, at the same time).
     const int32_t w = __builtin_amdgcn_readfirstlane(
-        (int32_t)(blockIdx.x * kWaves + (threadIdx.x >> 6)));
+        (int32_t)(xcd_chunk_block(blockIdx.x, gridDim.x, 16) * kWaves + (threadIdx.x >> 6)));
     nbr_search_wave(g, ng, xs, ys, zs, hs, off, perm, key, cnt, slots, w);
 }
 
 // Move every target's slot to its CSR row (or search again into the row
-// when the slot was too short).
-// Target s (uniform across the wavefront).
+// when the slot was too short).  Wavefront w takes targets
+// kCompact w .. kCompact w + kCompact - 1, 64 / kCompact lanes each; a target
+// with more than kSlot hits is searched again by the whole wavefront.
+constexpr int kCompact = 4;
+constexpr int kCompactLanes = 64 / kCompact;
+
 __device__ __attribute__((always_inline)) inline void nbr_compact_wave(
     const sg_grid_dev* __restrict__ g, int64_t ng, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ hs,
     const int64_t* __restrict__ off, const int32_t* __restrict__ cnt,
     const int32_t* __restrict__ slots, const int64_t* __restrict__ nbr_off,
-    int32_t* __restrict__ nbr_idx, int64_t s) {
+    int32_t* __restrict__ nbr_idx, int64_t w) {
     if (g->err & (SGE_SORT_FATAL | SGE_NNZ)) return;
     const unsigned lane = threadIdx.x & 63;
-    if (s >= ng) return;
-    const int64_t c = cnt[s], to = nbr_off[s];
+    const int64_t s0 = w * kCompact;
+    if (s0 >= ng) return;
+    const int64_t s = s0 + lane / kCompactLanes;
+    const int64_t c = s < ng ? cnt[s] : 0;
     if (c <= kSlot) {
         const int32_t* mine = slots + s * kSlot;
-        for (int64_t k = lane; k < c; k += 64) nbr_idx[to + k] = mine[k];
-        return;
+        const int64_t to = nbr_off[s < ng ? s : 0];
+        for (int64_t k = lane % kCompactLanes; k < c; k += kCompactLanes) nbr_idx[to + k] = mine[k];
     }
-    int64_t q = 0;
-    nbr_scan(g, ng, s, lane, xs, ys, zs, hs, off, [&](unsigned long long mask, int64_t t, bool ok) {
-        if (ok) nbr_idx[to + q + rank_below(mask)] = (int32_t)t;
-        q += __builtin_popcountll(mask);
-    });
+    for (int j = 0; j < kCompact; ++j) {
+        const int64_t sj = s0 + j;
+        if (sj >= ng) break;
+        const int64_t to = nbr_off[sj];
+        if (cnt[sj] <= kSlot) continue;
+        int64_t q = 0;
+        nbr_scan(g, ng, sj, lane, xs, ys, zs, hs, off,
+                 [&](unsigned long long mask, int64_t t, bool ok) {
+                     if (ok) nbr_idx[to + q + rank_below(mask)] = (int32_t)t;
+                     q += __builtin_popcountll(mask);
+                 });
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_nbr_compact(
@@ -338,8 +399,8 @@ __global__ __launch_bounds__(kBlock) void k_nbr_compact(
     const int64_t* __restrict__ off, const int32_t* __restrict__ cnt,
     const int32_t* __restrict__ slots, const int64_t* __restrict__ nbr_off,
     int32_t* __restrict__ nbr_idx) {
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-    nbr_compact_wave(g, ng, xs, ys, zs, hs, off, cnt, slots, nbr_off, nbr_idx, s);
+    const int64_t w = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    nbr_compact_wave(g, ng, xs, ys, zs, hs, off, cnt, slots, nbr_off, nbr_idx, w);
 }
 
 __device__ inline void nbr_check_one(sg_grid_dev* g, const int64_t* __restrict__ nbr_off,
@@ -395,16 +456,26 @@ inline unsigned waves_grid(int64_t n) {
 }  // namespace
 
 void sg_seg_launch_nbr_search(const sg_seg& s, hipStream_t st) {
-    if (s.nblk[SG_SEG_NG] > 0)
-        hipLaunchKernelGGL(k_seg_nbr_search, dim3((unsigned)s.nblk[SG_SEG_NG]), dim3(kBlock), 0, st,
-                           s.sys, s.pfx + SG_SEG_NG * (s.nsys + 1), s.nsys);
+    if (s.nblk[SG_SEG_NBR] > 0)
+        hipLaunchKernelGGL(k_seg_nbr_search, dim3((unsigned)s.nblk[SG_SEG_NBR]), dim3(kBlock), 0, st,
+                           s.sys, s.pfx + SG_SEG_NBR * (s.nsys + 1), s.nsys);
 }
 
 void sg_seg_launch_nbr_finish(const sg_seg& s, hipStream_t st) {
-    if (s.nblk[SG_SEG_NG4] == 0) return;
+    if (s.nblk[SG_SEG_CPT] == 0) return;
     hipLaunchKernelGGL(k_seg_nbr_check, dim3(1), dim3(64), 0, st, s.sys, s.nsys);
-    hipLaunchKernelGGL(k_seg_nbr_compact, dim3((unsigned)s.nblk[SG_SEG_NG4]), dim3(kBlock), 0, st,
-                       s.sys, s.pfx + SG_SEG_NG4 * (s.nsys + 1), s.nsys);
+    hipLaunchKernelGGL(k_seg_nbr_compact, dim3((unsigned)s.nblk[SG_SEG_CPT]), dim3(kBlock), 0, st,
+                       s.sys, s.pfx + SG_SEG_CPT * (s.nsys + 1), s.nsys);
+}
+
+int64_t sg_compact_blocks(int64_t ng) {
+    const int64_t per = (int64_t)kWaves * kCompact;
+    return (ng + per - 1) / per;
+}
+
+int64_t sg_nbr_blocks(int64_t ng) {
+    const int64_t per = (int64_t)kWaves * kTargets;
+    return (ng + per - 1) / per;
 }
 
 size_t sg_nbr_slot_bytes(int64_t ng) { return 4 * (size_t)kSlot * (size_t)(ng > 0 ? ng : 0); }
@@ -413,8 +484,8 @@ void sg_launch_nbr_search(const sg_grid_dev* g, int64_t ng, const double* xs, co
                           const double* zs, const double* hs, const int64_t* off,
                           const int32_t* perm, const int32_t* key, int32_t* cnt, int32_t* slots,
                           hipStream_t st) {
-    // one wavefront per 64 target slots
-    hipLaunchKernelGGL(k_nbr_search, dim3(waves_grid((ng + 63) / 64)), dim3(kBlock), 0, st, g, ng,
+    // one wavefront per kTargets target slots
+    hipLaunchKernelGGL(k_nbr_search, dim3(waves_grid((ng + kTargets - 1) / kTargets)), dim3(kBlock), 0, st, g, ng,
                        xs, ys, zs, hs, off, perm, key, cnt, slots);
 }
 
@@ -427,6 +498,7 @@ void sg_launch_nbr_compact(const sg_grid_dev* g, int64_t ng, const double* xs, c
                            const double* zs, const double* hs, const int64_t* off,
                            const int32_t* cnt, const int32_t* slots, const int64_t* nbr_off,
                            int32_t* nbr_idx, hipStream_t st) {
-    hipLaunchKernelGGL(k_nbr_compact, dim3(waves_grid(ng)), dim3(kBlock), 0, st, g, ng, xs, ys, zs,
+    hipLaunchKernelGGL(k_nbr_compact, dim3(waves_grid((ng + kCompact - 1) / kCompact)), dim3(kBlock),
+                       0, st, g, ng, xs, ys, zs,
                        hs, off, cnt, slots, nbr_off, nbr_idx);
 }

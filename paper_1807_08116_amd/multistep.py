@@ -119,10 +119,12 @@ def main():
 
 def gaps(a, b):
     """Largest gaps between two histories of the conserved sums (same steps):
-    total energy relative to |E(0)| of the second, momentum and angular
-    momentum absolute."""
+    total energy relative to |E(0)| of the second (values, and changes
+    since step 0), momentum and angular momentum absolute."""
     return {
         "energy_gap_max": float(np.max(np.abs(a[:, 3] - b[:, 3]) / abs(b[0, 3]))),
+        "energy_change_gap_max": float(np.max(np.abs((a[:, 3] - a[0, 3]) - (b[:, 3] - b[0, 3]))
+                                              / abs(b[0, 3]))),
         "momentum_gap_max": float(np.max(np.linalg.norm(a[:, 4:7] - b[:, 4:7], axis=1))),
         "angmom_gap_max": float(np.max(np.linalg.norm(a[:, 7:10] - b[:, 7:10], axis=1))),
     }
