@@ -114,13 +114,18 @@ def run_form(sg, st, precision, steps, warmup, sample, tune):
         ctx.diagnostics(diag)
     ctx.sync()
     ctx.profile_enable(True)
+    # per-step events on the context's stream (no host waits between steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    evs[0].record(ctx.stream)
+    for k in range(steps):
         ctx.step(DT, sg.SG_POT)
         ctx.diagnostics(diag)
+        evs[k + 1].record(ctx.stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     ctx.sync()
@@ -143,7 +148,7 @@ def run_form(sg, st, precision, steps, warmup, sample, tune):
     eng.ctx.close()
     del eng
     torch.cuda.empty_cache()
-    return {"sec": (t1 - t0), "acc": acc, "parts": parts, "prof": prof,
+    return {"sec": (t1 - t0), "step_ms": step_ms, "acc": acc, "parts": parts, "prof": prof,
             "prof_serial": prof_serial, "diag": d.tolist(), "nnz": nnz, "ncell": ncell}
 
 
@@ -219,7 +224,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only", choices=["fp32c", "fp64", "both"], default="both")
@@ -318,6 +323,8 @@ def main():
         out[form] = {
             "steps_per_s": args.steps / res[form]["sec"],
             "ms_per_step": 1e3 * res[form]["sec"] / args.steps,
+            "ms_per_step_events": res[form]["step_ms"],
+            "ms_per_step_median": float(np.median(res[form]["step_ms"])),
             "stage_ms_per_step": {k: v[0] / args.steps for k, v in pr.items()},
             "stage_note": "stages of the timed steps; the neighbour, density and SPH stages "
                           "run beside the gravity kernel, so their times include waiting "

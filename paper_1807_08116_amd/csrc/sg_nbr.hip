@@ -44,9 +44,6 @@ constexpr int kWaves = kBlock / 64;
 // and 1.57 ms with 16 (each run cut at a wavefront boundary repeats its
 // boxes' setup and candidate loads).
 constexpr int kTargets = 32;
-#ifndef SG_NBR_PAIR
-#define SG_NBR_PAIR 0
-#endif
 
 __device__ inline unsigned rank_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
@@ -278,59 +275,28 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                     }
                     const int32_t trel = (int32_t)(t - g0);      // |t - g0| < ng
                     // every target of the run against these 64 candidates
-#if SG_NBR_PAIR
-                    // two targets per pass: their tests are independent
-                    for (unsigned long long tr = run; tr;) {
-                        const int La = __builtin_ctzll(tr);
-                        tr &= tr - 1;
-                        const bool two = tr != 0;
-                        const int Lb = two ? __builtin_ctzll(tr) : La;
-                        if (two) tr &= tr - 1;
-                        const double xa = lane_f64(p[0], La), ya = lane_f64(p[1], La);
-                        const double za = lane_f64(p[2], La);
-                        const float ha = lane_f32(hif, La);
-                        const double xb = lane_f64(p[0], Lb), yb = lane_f64(p[1], Lb);
-                        const double zb = lane_f64(p[2], Lb);
-                        const float hb = lane_f32(hif, Lb);
-                        const bool oka = nbr_pred_f(xa, ya, za, ha, xj, yj, zj, hjf) & valid &
-                                         (trel != La);
-                        const bool okb = nbr_pred_f(xb, yb, zb, hb, xj, yj, zj, hjf) & valid &
-                                         (trel != Lb) & two;
-                        const unsigned long long ma = __ballot(oka), mb = __ballot(okb);
-                        if (ma) {
-                            const int32_t c0 = __builtin_amdgcn_readlane(mine, La);
-                            const int32_t pos = c0 + (int32_t)rank_below(ma);
-                            if (oka && pos < kSlot) slots[(g0 + La) * kSlot + pos] = (int32_t)t;
-                            if (lane == (unsigned)La) mine = c0 + __builtin_popcountll(ma);
-                        }
-                        if (mb) {
-                            const int32_t c0 = __builtin_amdgcn_readlane(mine, Lb);
-                            const int32_t pos = c0 + (int32_t)rank_below(mb);
-                            if (okb && pos < kSlot) slots[(g0 + Lb) * kSlot + pos] = (int32_t)t;
-                            if (lane == (unsigned)Lb) mine = c0 + __builtin_popcountll(mb);
-                        }
-                    }
-#else
                     for (unsigned long long tr = run; tr; tr &= tr - 1) {
                         const int L = __builtin_ctzll(tr);
                         const int64_t sL = g0 + L;
                         // target L's data, read across lanes with every lane
                         // active (a lane read inside a divergent branch may
-                        // see a register the branch did not write for it)
+                        // see a register the branch did not write for it);
+                        // loading it by scalar loads instead waits for the
+                        // scalar cache every pass (stage 1.54 -> 2.0 ms)
                         const double xi = lane_f64(p[0], L), yi = lane_f64(p[1], L);
                         const double zi = lane_f64(p[2], L);
                         const float hi = lane_f32(hif, L);
                         const bool ok = nbr_pred_f(xi, yi, zi, hi, xj, yj, zj, hjf) & valid &
                                         (trel != L);
-                        const unsigned long long mask = __ballot(ok);
+                        const unsigned long long mask = __builtin_amdgcn_ballot_w64(ok);
                         if (mask) {
                             const int32_t c0 = __builtin_amdgcn_readlane(mine, L);
-                            const int32_t pos = c0 + (int32_t)rank_below(mask);
-                            if (ok && pos < kSlot) slots[sL * kSlot + pos] = (int32_t)t;
+                            const uint32_t pos = (uint32_t)c0 + (uint32_t)rank_below(mask);
+                            int32_t* const row = slots + sL * kSlot;
+                            if (ok && pos < (uint32_t)kSlot) row[pos] = (int32_t)t;
                             if (lane == (unsigned)L) mine = c0 + __builtin_popcountll(mask);
                         }
                     }
-#endif
                 }
             }
         }

@@ -299,6 +299,31 @@ def test_edge_sizes(sg, orc, ng, nh, dup):
     assert e32 < FP32C_TOL
 
 
+# Gas counts around the block-order chunk boundaries: the neighbour search
+# deals 16-workgroup chunks (128 targets each) and the density and force
+# passes 64-workgroup chunks (32 targets each) to the XCDs, so 16384 gas
+# particles fill exactly one round of chunks in both; one fewer leaves the
+# last workgroup partial, one more adds a workgroup outside the chunks,
+# and 40000 gives two rounds plus a tail.
+@pytest.mark.parametrize("ng", [16383, 16385, 40000])
+def test_block_order_boundaries(sg, orc, ng):
+    from paper_1807_08116_amd import ic
+    rng = np.random.default_rng(ng)
+    st = _random_state(rng, ng, 64)
+    st["h"] *= (1000.0 / ng) ** (1.0 / 3.0)            # about 50 neighbours per gas particle
+    ref = orc.forces(st, ic.DEFAULT_PARAMS)
+    s, nb, soff, sidx = oracle_sort_and_rows(orc, st)
+    A = oracle_accel(orc, st, ref)
+    for prec, tol in ((sg.SG_FP64, FP64_TOL), (sg.SG_FP32C, FP32C_TOL)):
+        eng = sg.Engine(st, precision=prec)
+        full_eval(eng, sg)
+        check_sort_bitexact(sg, eng, s, soff, sidx, orc)
+        e_rho = nrm_err(eng.numpy("rho")[:ng], ref["rho"])
+        e_acc = nrm_err(gpu_accel(eng), A)
+        print("block order", ng, prec, "nnz", len(sidx), "rho %.2e acc %.2e" % (e_rho, e_acc))
+        assert e_rho < tol and e_acc < tol
+
+
 def test_capacity_overflow_and_retry(sg, orc, c0, c0_ref):
     ref, s, soff, sidx = c0_ref
     caps = sg.default_caps(c0["ng"], len(c0["x"]) - c0["ng"], cell_cap=10, nnz_cap=100)
