@@ -330,12 +330,18 @@ sg_status sg_status_sync(sg_ctx *ctx, int64_t need[2]);
  * (system, block of 256 * grav_ipl targets) tasks, largest systems first,
  * from a device counter until none is left; grav_ipl and grav_tile are
  * those of the first context, 0 selecting 2 targets per lane and 512
- * sources per tile for this launch.  The per-particle stages of a step
- * (the predictor's SPH pass, the combination of the SPH and gravity parts,
- * predictor and corrector, the Morton order and sorted copies of the
- * gravity inputs) also run as one launch each for all systems; only the
- * corrector's neighbour build, density and SPH pass run system by system,
- * beside the gravity kernel.
+ * sources per tile for this launch.  Every other per-particle stage of a
+ * step (the predictor's SPH pass, the combination of the SPH and gravity
+ * parts, predictor and corrector, the Morton order and sorted copies of the
+ * gravity inputs, and the corrector's grid, sort, neighbour lists, density
+ * and SPH pass) also runs as one launch for all systems, over a device
+ * table of the systems' pointers; a stage that only some systems need (a
+ * context whose lists are still valid) runs system by system instead.
+ * Device-side conditions (capacity overflow, non-finite values) are latched
+ * in each context's own status word, as for single contexts: the ensemble
+ * calls report only enqueue and host errors, and the caller reads each
+ * context's conditions with sg_status_sync(ctx) (after sg_ensemble_run,
+ * which has waited already, that call returns at once).
  * The ensemble keeps pointers into the contexts: do not rebind or destroy
  * them while it exists.  d_ws: caller-owned device memory of
  * sg_ensemble_bytes(nsys, total particles), 256-byte aligned; the task and

@@ -451,6 +451,12 @@ class Ensemble:
         self.stream = torch.cuda.Stream(device=dev)
         self.engines = [Engine(st, precision=SG_FP32C, device=device, stream=self.stream,
                                aux_stream=None, **kw) for st in states]
+        # size each system's grid and list capacities for its initial state
+        # (a build per system; the ensemble keeps the contexts' pointers, so
+        # they cannot grow once it exists)
+        for e in self.engines:
+            if e.ng > 0:
+                e.build_neighbors()
         total = sum(e.n for e in self.engines)
         L = lib()
         nbytes = L.sg_ensemble_bytes(len(self.engines), total)
@@ -485,6 +491,17 @@ class Ensemble:
     def run(self, dt, nsteps, flags=0, use_graph=True):
         self._check(lib().sg_ensemble_run(self.h, float(dt), int(nsteps), flags,
                                           1 if use_graph else 0), "sg_ensemble_run")
+        self.sync()
+
+    def sync(self):
+        """Wait for the stream and raise SGError (with .system, .need) for the
+        first system whose device status word holds a condition."""
+        for k, e in enumerate(self.engines):
+            try:
+                e.ctx.sync()
+            except SGError as err:
+                err.system = k
+                raise
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -98,6 +98,44 @@ def test_ensemble_steps_match_single_and_graph(sg, states):
             np.testing.assert_array_equal(a, c, err_msg="single " + f)
 
 
+def _small_state(rng, ng, nh):
+    n = ng + nh
+    pos = rng.normal(size=(n, 3))
+    return {"ng": ng, "x": pos[:, 0].copy(), "y": pos[:, 1].copy(), "z": pos[:, 2].copy(),
+            "vx": rng.normal(size=n) * 0.1, "vy": rng.normal(size=n) * 0.1,
+            "vz": rng.normal(size=n) * 0.1, "m": rng.uniform(0.5, 1.5, n) / max(n, 1),
+            "e": rng.uniform(0.02, 0.08, ng),
+            "h": rng.uniform(0.1, 0.4, ng) * (1 + np.abs(pos[:ng, 0])) * (50.0 / max(ng, 50)) ** (1 / 3)}
+
+
+def test_ensemble_edge_systems(sg):
+    # systems at the edges of the segmented launches' block prefixes: one
+    # gas particle and no halo, no gas at all, fewer gas particles than one
+    # workgroup of any stage, and sizes that end mid-workgroup; steps of the
+    # ensemble (eager and graph-captured) equal each system's own steps
+    rng = np.random.default_rng(2024)
+    sizes = [(1, 0), (0, 7), (33, 0), (257, 40), (2000, 500), (4097, 3)]
+    states = [_small_state(rng, ng, nh) for ng, nh in sizes]
+    dt = 1e-3
+    eager = sg.Ensemble(states, grav_ipl=2)
+    eager.run(dt, 3, sg.SG_POT, use_graph=False)
+    graph = sg.Ensemble(states, grav_ipl=2)
+    graph.run(dt, 3, sg.SG_POT, use_graph=True)
+    for (ng, nh), st, e1, e2 in zip(sizes, states, eager.engines, graph.engines):
+        single = sg.Engine(st, precision=sg.SG_FP32C, grav_split=1, grav_ipl=2, grav_tile=512)
+        if ng > 0:
+            single.build_neighbors()          # capacities for the initial state, as the ensemble
+        for _ in range(3):
+            single.ctx.step(dt, sg.SG_POT)
+        single.ctx.sync()
+        fields = ("x", "y", "z", "vx", "vy", "vz", "ax", "pot") + (("e", "rho") if ng else ())
+        for f in fields:
+            a, b, c = e1.numpy(f), e2.numpy(f), single.numpy(f)
+            assert np.all(np.isfinite(a)), (ng, nh, f)
+            np.testing.assert_array_equal(a, b, err_msg="graph %d/%d %s" % (ng, nh, f))
+            np.testing.assert_array_equal(a, c, err_msg="single %d/%d %s" % (ng, nh, f))
+
+
 # ------------------------------------------------- full ensemble size --
 
 @pytest.fixture(scope="module")
