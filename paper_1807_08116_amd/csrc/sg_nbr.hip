@@ -24,8 +24,9 @@
 // Each target writes its hits into a slot of its own, kSlot entries long,
 // in a scratch array (no atomics), and counts them.  A scan of the counts
 // gives the CSR offsets; a copy pass then moves every slot to its CSR row,
-// and a target with more than kSlot hits (none in the workloads measured:
-// at most 58) searches a second time, alone, straight into its row.
+// and a target with more than kSlot hits (none in the collision workloads:
+// at most 58 at 2M particles; clustered gas can have thousands) searches a
+// second time, alone, straight into its row.
 //
 // Built with -ffp-contract=off: the FP32 predicate must round exactly as
 // specified (each product and fma rounded once).
@@ -36,13 +37,13 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 // Targets per wavefront of the search (lanes 0 .. kTargets-1 hold them;
-// all 64 lanes hold candidates).  The wavefronts' work varies widely (runs
-// of 1 to 64 targets, union boxes over 1 to 5 levels), and a resident
-// wavefront issues about one instruction in 18 cycles, so the launch is
-// bound by how well the wavefronts pack the SIMDs: at 2M particles the
-// search stage took 1.62 ms with 64 targets per wavefront, 1.53 ms with 32
-// and 1.57 ms with 16 (each run cut at a wavefront boundary repeats its
-// boxes' setup and candidate loads).
+// all 64 lanes hold candidates).  The search is bound by the vector-ALU
+// work of its pair tests (busy over 90 % of the kernel at 2M particles),
+// and the wavefronts' work varies widely (runs of 1 to 64 targets, union
+// boxes over 1 to 5 levels), so shorter wavefronts pack the SIMDs better
+// at the end of the launch: the search stage took 1.62 ms with 64 targets
+// per wavefront, 1.53 ms with 32 and 1.57 ms with 16 (each run cut at a
+// wavefront boundary repeats its boxes' setup and candidate loads).
 constexpr int kTargets = 32;
 
 __device__ inline unsigned rank_below(unsigned long long mask) {
