@@ -42,13 +42,14 @@ def pass_bytes(stage, precision_form, ng, nnz, ncell):
     array the stage must read or write, counted once (per gas particle, per
     neighbour pair, per cell)."""
     if stage == "sort":
-        # keys: x,y,z,h in (32 B), key out (4), count and max-h atomics (12);
-        # radix passes: the first reads keys (histogram and scatter, 8 B)
-        # and writes key and id (8), each later one reads and writes both
-        # (4 + 16); gather: perm and x,y,z,h,m in (44), sorted copies and the
-        # density records out (104); cells: count, max h, offset (24)
+        # keys: x,y,z,h,m in (40 B), key out (4), count and max-h atomics
+        # (12), the particle's 64-byte record out (for the gather); radix
+        # passes: the first reads keys (histogram and scatter, 8 B) and
+        # writes key and id (8), each later one reads and writes both
+        # (4 + 16); gather: perm and the record in (68), sorted copies and
+        # the density records out (104); cells: count, max h, offset (24)
         p = radix_passes(8 * ng + 4096)      # the binding's default cell capacity
-        return (48 + 16 + 20 * (p - 1) + 148) * ng + 24 * ncell
+        return (120 + 16 + 20 * (p - 1) + 172) * ng + 24 * ncell
     if stage == "nbr":         # own x,y,z,h; count + offset; one int32 per pair
         return 44 * ng + 4 * nnz
     if stage == "density":     # offset, record (64 B), rho out; one index per pair

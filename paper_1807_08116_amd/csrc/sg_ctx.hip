@@ -83,7 +83,9 @@ layout make_layout(const sg_params* p, const sg_caps* c) {
     size_t* f64s[] = {&L.xs, &L.ys, &L.zs, &L.hs, &L.ms, &L.rho_s};
     for (size_t* q : f64s) *q = take(8 * ng);
     L.prec = take(sizeof(sg_prec) * ng);
-    L.f64 = take(sizeof(sg_frec64) * ng);          // also used by the time-step rule
+    // FP64 force records, also the time-step rule's; between uses the sort
+    // borrows the buffer for its particle-order records (64 of 96 bytes)
+    L.f64 = take(sizeof(sg_frec64) * ng);
     L.f32 = take(f32 ? sizeof(sg_frec32) * ng : 0);
     L.ncnt = take(4 * ng);
     L.nbr_off = take(8 * (ng + 1));
@@ -332,11 +334,14 @@ sg_status do_build(sg_ctx* c) {
     sg_launch_grid_reduce(s.x, s.y, s.z, s.h, ng, g, st);
     sg_launch_grid_finish(g, C, c->prm.cell_scale_log2, st);
     sg_launch_cells_clear(g, count, hmax, C, st);
-    sg_launch_keys_count(s.x, s.y, s.z, s.h, ng, g, key, count, hmax, st);
+    // the FP64 force records are rebuilt before every use (record builds
+    // precede each force and time-step pass), so the sort borrows their
+    // buffer for the particle-order records the gather reads
+    sg_prec* pin = reinterpret_cast<sg_prec*>(b.f64);
+    sg_launch_keys_count(s.x, s.y, s.z, s.h, s.m, ng, g, key, count, hmax, pin, st);
     sg_launch_scan(count, off, 0, &g->M, C, scan, st);
     sg_launch_gas_order(key, ng, C, c->at<void>(c->L.gsort), c->at<int32_t>(c->L.perm), st);
-    sg_launch_gather_gas(b.perm, ng, g, s.x, s.y, s.z, s.h, s.m, b.xs, b.ys, b.zs, b.hs, b.ms,
-                         b.prec, st);
+    sg_launch_gather_gas(b.perm, ng, g, pin, b.xs, b.ys, b.zs, b.hs, b.ms, b.prec, st);
     c->end();
     c->begin(SG_ST_NBR);
     int32_t* ncnt = c->at<int32_t>(c->L.ncnt);

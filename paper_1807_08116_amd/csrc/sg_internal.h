@@ -114,19 +114,21 @@ void sg_launch_grid_reduce(const double* x, const double* y, const double* z, co
 void sg_launch_grid_finish(sg_grid_dev* g, int64_t cell_cap, int cell_scale_log2, hipStream_t st);
 void sg_launch_cells_clear(sg_grid_dev* g, int32_t* count, unsigned long long* hmax,
                            int64_t cell_cap, hipStream_t st);
+// Cell keys, per-cell counts and max h; also each particle's record
+// (x, y, z, h, m) in particle order into pin [ng] (scratch the gather reads).
+struct sg_prec;
 void sg_launch_keys_count(const double* x, const double* y, const double* z, const double* h,
-                          int64_t ng, sg_grid_dev* g, int32_t* key, int32_t* count,
-                          unsigned long long* hmax, hipStream_t st);
+                          const double* m, int64_t ng, sg_grid_dev* g, int32_t* key,
+                          int32_t* count, unsigned long long* hmax, sg_prec* pin,
+                          hipStream_t st);
 // Stable order of the gas by cell key (ascending id inside a cell): LSD
 // radix sort of the keys with 10-bit digits, enough passes for keys below
 // cell_cap; tmp: sg_morton_tmp_bytes(ng) bytes.
 int sg_gas_radix_passes(int64_t cell_cap);
 void sg_launch_gas_order(const int32_t* key, int64_t ng, int64_t cell_cap, void* tmp,
                          int32_t* perm, hipStream_t st);
-struct sg_prec;
 void sg_launch_gather_gas(const int32_t* perm, int64_t ng, const sg_grid_dev* g,
-                          const double* x, const double* y, const double* z, const double* h,
-                          const double* m, double* xs, double* ys, double* zs, double* hs,
+                          const sg_prec* pin, double* xs, double* ys, double* zs, double* hs,
                           double* ms, sg_prec* prec, hipStream_t st);
 
 // Neighbour lists.
