@@ -54,8 +54,9 @@ def pass_bytes(stage, precision_form, ng, nnz, ncell):
         return 44 * ng + 4 * nnz
     if stage == "density":     # offset, record (64 B), rho out; one index per pair
         return 80 * ng + 4 * nnz
-    if stage == "sph":         # EOS + record build, then offsets, records, 4 outputs
-        return (336 if precision_form == "fp64" else 272) * ng + 4 * nnz
+    if stage == "sph":         # v, e packed (32 B in, 32 out), EOS + record build
+        #                        (reads the pack), then offsets, records, 4 outputs
+        return (400 if precision_form == "fp64" else 336) * ng + 4 * nnz
     raise ValueError(stage)
 
 

@@ -264,6 +264,7 @@ struct sg_ctx {
         b.perm = at<int32_t>(L.perm);
         b.nbr_off = at<int64_t>(L.nbr_off);
         b.nbr_idx = at<int32_t>(L.nbr_idx);
+        b.ve = at<double>(L.nbr_slots);
         return b;
     }
     void invalidate_positions() {

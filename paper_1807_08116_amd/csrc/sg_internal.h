@@ -167,6 +167,10 @@ struct sg_sph_bufs {
     const int32_t* perm;
     const int64_t* nbr_off;
     const int32_t* nbr_idx;
+    // (vx, vy, vz, e) of each gas particle in particle order, 32 bytes each,
+    // packed for the record build's random reads; it borrows the
+    // neighbour-search slots, which are free once the lists are copied
+    double* ve;
 };
 void sg_launch_density(const sg_sph_bufs& b, const sg_grid_dev* g, int64_t ng, int precision,
                        double* rho_out, hipStream_t st);
