@@ -284,6 +284,7 @@ class Context:
                                     device=self.device)
         self._check(lib().sg_run(self.h, float(dt), int(nsteps), flags, 1 if use_graph else 0,
                                  C.c_void_p(hist.data_ptr())), "sg_run")
+        self.sync()                 # sg_run has waited: report latched device conditions
         return hist
 
     def cfl_dt(self, C=0.5, out=None):
