@@ -136,6 +136,22 @@ def test_ensemble_edge_systems(sg):
             np.testing.assert_array_equal(a, c, err_msg="single %d/%d %s" % (ng, nh, f))
 
 
+def test_ensemble_reports_a_system_overflow(sg):
+    # a system whose gas spreads far beyond what its grid capacity was sized
+    # for latches SG_ECAPACITY in its own status word; the ensemble run
+    # reports it with the system's index
+    rng = np.random.default_rng(5)
+    states = [_small_state(rng, 300, 10) for _ in range(3)]
+    ens = sg.Ensemble(states, grav_ipl=2)
+    eng = ens.engines[1]
+    eng.dev["x"][:eng.ng] *= 10.0          # about 4.6e5 cells needed, 6496 sized
+    eng.dev["y"][:eng.ng] *= 10.0
+    with pytest.raises(sg.SGError) as ei:
+        ens.run(1e-3, 1, sg.SG_POT, use_graph=False)
+    assert ei.value.code == sg.SG_ECAPACITY
+    assert ei.value.system == 1 and ei.value.need[0] > eng.caps.cell_cap
+
+
 # ------------------------------------------------- full ensemble size --
 
 @pytest.fixture(scope="module")
