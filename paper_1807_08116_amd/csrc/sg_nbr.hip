@@ -273,8 +273,9 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                 // chunk (its data read across lanes once per chunk, its hit
                 // count carried in a scalar register)
                 for (int32_t cb0 = 0; cb0 < total; cb0 += 64 * kHold) {
-                    int32_t tk[kHold], trk[kHold];
+                    int32_t tk[kHold];
                     bool vk[kHold];
+                    unsigned long long vm[kHold];          // lanes holding a candidate
                     double xk[kHold], yk[kHold], zk[kHold];
                     float hk[kHold];
 #pragma unroll
@@ -293,7 +294,8 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                                 hk[k] = (float)hs[tk[k]];
                             }
                         }
-                        trk[k] = (int32_t)(tk[k] - g0);       // |t - g0| < ng
+                        const int32_t nk = total - (cb0 + 64 * k);
+                        vm[k] = nk >= 64 ? ~0ull : (nk > 0 ? (1ull << nk) - 1 : 0ull);
                     }
                     for (unsigned long long tr = run; tr; tr &= tr - 1) {
                         const int L = __builtin_ctzll(tr);
@@ -309,12 +311,17 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
 #pragma unroll
                         for (int k = 0; k < kHold; ++k) {
                             if (cb0 + 64 * k >= total) break;  // uniform
-                            const bool ok = nbr_pred_f(xi, yi, zi, hi, xk[k], yk[k], zk[k], hk[k]) &
-                                            vk[k] & (trk[k] != L);
-                            const unsigned long long mask = __builtin_amdgcn_ballot_w64(ok);
+                            // the ballot of the bare comparison is the
+                            // comparison's own lane mask and validity a
+                            // scalar mask; the target itself is looked for
+                            // only in batches with a hit
+                            const bool pr = nbr_pred_f(xi, yi, zi, hi, xk[k], yk[k], zk[k], hk[k]);
+                            unsigned long long mask = __builtin_amdgcn_ballot_w64(pr) & vm[k];
                             if (mask) {
+                                const bool me = tk[k] == (int32_t)sL;
+                                mask &= ~__builtin_amdgcn_ballot_w64(me);
                                 const uint32_t pos = (uint32_t)c + (uint32_t)rank_below(mask);
-                                if (ok && pos < (uint32_t)kSlot) row[pos] = tk[k];
+                                if (pr && vk[k] && !me && pos < (uint32_t)kSlot) row[pos] = tk[k];
                                 c += __builtin_popcountll(mask);
                             }
                         }
