@@ -16,10 +16,13 @@
 // its targets' boxes.  The rows of that region are flattened into one
 // candidate stream, loaded 256 candidates at a time (four per lane) and
 // held in registers while every target of the run tests them, so a
-// candidate is fetched once per cell instead of once per target.  Any grouping gives
-// the same lists: the union contains each target's own box, and every
-// target keeps only the candidates that pass its predicate, in stream
-// order.
+// candidate is fetched once per cell instead of once per target.  Any
+// grouping gives the same lists: the union contains each target's own box,
+// and every target keeps only the candidates that pass its predicate, in
+// stream order.  The union box is a pair of DPP reductions per dimension,
+// the stream offsets a DPP scan of the row lengths, and each batch of 64
+// stream positions finds its slots by walking the few non-empty rows that
+// overlap it: the set-up makes no LDS round trips.
 //
 // Each target writes its hits into a slot of its own, kSlot entries long,
 // in a scratch array (no atomics), and counts them.  A scan of the counts
@@ -88,7 +91,7 @@ constexpr int64_t kSlot = 96;              // scratch entries per target
 // Cells [lo, hi] (per dimension, clamped to the grid) of level l within
 // R = (h + hmax_l)(1 + 2^-10) of p; false when the level has no such cell.
 __device__ inline bool level_box(const sg_grid_dev* __restrict__ g, int l, const double p[3],
-                                 double h, int64_t lo[3], int64_t hi3[3]) {
+                                 double h, int32_t lo[3], int32_t hi3[3]) {
     const double R = (h + g->hmaxlev[l]) * (1.0 + 0x1p-10);
     const double inv = g->invL[l];
     bool empty = false;
@@ -100,8 +103,8 @@ __device__ inline bool level_box(const sg_grid_dev* __restrict__ g, int l, const
         if (b < 0.0 || a > top) empty = true;
         a = a < 0.0 ? 0.0 : (a > top ? top : a);
         b = b < 0.0 ? 0.0 : (b > top ? top : b);
-        lo[d] = (int64_t)a;
-        hi3[d] = (int64_t)b;
+        lo[d] = (int32_t)a;                  // in [0, dim - 1]: cell indices fit int32
+        hi3[d] = (int32_t)b;
     }
     return !empty;
 }
@@ -119,11 +122,11 @@ __device__ inline void nbr_scan(const sg_grid_dev* __restrict__ g, int64_t ng, i
     const int nlev = g->nlev;
     for (int l = 0; l < nlev; ++l) {
         if (g->ncell[l] == 0) continue;
-        int64_t lo[3], hi3[3];
+        int32_t lo[3], hi3[3];
         if (!level_box(g, l, p, hi, lo, hi3)) continue;
         const int64_t base = g->base[l], dx = g->dim[l][0], dy = g->dim[l][1];
-        const int64_t ny = hi3[1] - lo[1] + 1;
-        const int64_t nrows = (hi3[2] - lo[2] + 1) * ny;
+        const int64_t ny = (int64_t)hi3[1] - lo[1] + 1;
+        const int64_t nrows = ((int64_t)hi3[2] - lo[2] + 1) * ny;
         for (int64_t r0 = 0; r0 < nrows; r0 += 64) {
             // bounds of rows r0 .. r0+63, one row per lane; offsets are
             // bounded by ng: clamp so that a corrupt table can never send a
@@ -152,28 +155,48 @@ __device__ inline void nbr_scan(const sg_grid_dev* __restrict__ g, int64_t ng, i
     }
 }
 
-__device__ inline int32_t wave_min(int32_t v) {
-    for (int o = 32; o >= 1; o >>= 1) {
-        const int32_t u = __shfl_xor(v, o, 64);
-        v = u < v ? u : v;
-    }
-    return v;
+// Cross-lane reductions and scan by DPP row operations (no LDS round
+// trips; every lane of the wavefront must be active).  Controls:
+// quad_perm [1,0,3,2] 0xb1, [2,3,0,1] 0x4e, row_shr:n 0x110 + n,
+// row_mirror 0x140, row_half_mirror 0x141, row_bcast:15 0x142 (lane 15 of
+// each row into the next row), row_bcast:31 0x143 (lane 31 into rows 2, 3).
+template <int kCtrl, int kRowMask = 0xf>
+__device__ inline int32_t dpp(int32_t old, int32_t v) {
+    return __builtin_amdgcn_update_dpp(old, v, kCtrl, kRowMask, 0xf, false);
 }
 
+// minimum over the 64 lanes (uniform result)
+__device__ inline int32_t wave_min(int32_t v) {
+    constexpr int32_t I = INT32_MAX;
+    v = min(v, dpp<0xb1>(I, v));
+    v = min(v, dpp<0x4e>(I, v));
+    v = min(v, dpp<0x141>(I, v));
+    v = min(v, dpp<0x140>(I, v));              // each row of 16: its minimum
+    v = min(v, dpp<0x142, 0xa>(I, v));         // rows 1, 3: with rows 0, 2
+    v = min(v, dpp<0x143, 0xc>(I, v));         // rows 2, 3: with rows 0, 1
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// maximum over the 64 lanes (uniform result)
 __device__ inline int32_t wave_max(int32_t v) {
-    for (int o = 32; o >= 1; o >>= 1) {
-        const int32_t u = __shfl_xor(v, o, 64);
-        v = u > v ? u : v;
-    }
-    return v;
+    constexpr int32_t I = INT32_MIN;
+    v = max(v, dpp<0xb1>(I, v));
+    v = max(v, dpp<0x4e>(I, v));
+    v = max(v, dpp<0x141>(I, v));
+    v = max(v, dpp<0x140>(I, v));
+    v = max(v, dpp<0x142, 0xa>(I, v));
+    v = max(v, dpp<0x143, 0xc>(I, v));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // inclusive prefix sum over the 64 lanes
-__device__ inline int32_t wave_incl_sum(int32_t v, unsigned lane) {
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(v, o, 64);
-        if (lane >= (unsigned)o) v += u;
-    }
+__device__ inline int32_t wave_incl_sum(int32_t v) {
+    v += dpp<0x111>(0, v);                     // within each row of 16
+    v += dpp<0x112>(0, v);
+    v += dpp<0x114>(0, v);
+    v += dpp<0x118>(0, v);
+    v += dpp<0x142, 0xa>(0, v);                // rows 1, 3: + total of rows 0, 2
+    v += dpp<0x143, 0xc>(0, v);                // rows 2, 3: + total of rows 0, 1
     return v;
 }
 
@@ -224,29 +247,36 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
         const bool inrun = (run >> lane) & 1ull;
         for (int l = 0; l < nlev; ++l) {
             if (g->ncell[l] == 0) continue;
-            int64_t lo[3], hi3[3];
+            int32_t lo[3], hi3[3];
             const bool has = inrun && level_box(g, l, p, h, lo, hi3);
-            // union of the run's boxes (cell indices fit int32: keys do);
-            // wave-uniform, held in scalar registers so that every loop
-            // below is uniform and its cross-lane reads see all lanes
+            // union of the run's boxes; wave-uniform, held in scalar
+            // registers so that every loop below is uniform and its
+            // cross-lane reads see all lanes
             int32_t ulo[3], uhi[3];
+            bool inside = true;
             for (int d = 0; d < 3; ++d) {
-                ulo[d] = __builtin_amdgcn_readfirstlane(wave_min(has ? (int32_t)lo[d] : INT32_MAX));
-                uhi[d] = __builtin_amdgcn_readfirstlane(wave_max(has ? (int32_t)hi3[d] : -1));
+                ulo[d] = wave_min(has ? lo[d] : INT32_MAX);
+                uhi[d] = wave_max(has ? hi3[d] : -1);
+                inside = inside && ulo[d] >= 0 && ulo[d] <= uhi[d] && uhi[d] < g->dim[l][d];
             }
-            if (uhi[0] < 0) continue;          // no target of the run reaches level l
-            const int64_t base = g->base[l], dx = g->dim[l][0], dy = g->dim[l][1];
-            const int64_t ny = (int64_t)uhi[1] - ulo[1] + 1;
-            const int64_t nrows = ((int64_t)uhi[2] - ulo[2] + 1) * ny;
-            for (int64_t r0 = 0; r0 < nrows; r0 += 64) {
+            // no target of the run reaches level l (the box test also
+            // keeps every row and cell index below inside the level)
+            if (!inside) continue;
+            const int64_t base = g->base[l];
+            const int32_t dx = (int32_t)g->dim[l][0], dy = (int32_t)g->dim[l][1];
+            const uint32_t ny = (uint32_t)(uhi[1] - ulo[1] + 1);
+            const int32_t nrows = (int32_t)((uint32_t)(uhi[2] - ulo[2] + 1) * ny);
+            for (int32_t r0 = 0; r0 < nrows; r0 += 64) {
                 // rows r0 .. r0+63, one per lane: first slot and length
                 // (offsets clamped to [0, ng] so that a corrupt table can
-                // never send a load outside the sorted arrays)
+                // never send a load outside the sorted arrays); row and
+                // cell indices fit int32 (a level's cell count does)
                 int32_t first = 0, len = 0;
-                const int64_t r = r0 + lane;
+                const int32_t r = r0 + (int32_t)lane;
                 if (r < nrows) {
-                    const int64_t cz = ulo[2] + r / ny, cy = ulo[1] + r % ny;
-                    const int64_t row = base + (cz * dy + cy) * dx;
+                    const uint32_t rz = (uint32_t)r / ny;
+                    const int32_t cz = ulo[2] + (int32_t)rz, cy = ulo[1] + (int32_t)((uint32_t)r - rz * ny);
+                    const int64_t row = base + (int64_t)((cz * dy + cy) * dx);
                     int64_t a = off[row + ulo[0]], b = off[row + uhi[0] + 1];
                     a = a < 0 ? 0 : (a > ng ? ng : a);
                     b = b < a ? a : (b > ng ? ng : b);
@@ -255,18 +285,25 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                 }
                 // flatten: the rows are disjoint slot ranges, so the total
                 // is at most ng
-                const int32_t incl = wave_incl_sum(len, lane);
+                const int32_t incl = wave_incl_sum(len);
                 const int32_t start = incl - len;
-                const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
-                // stream position q -> slot: the row holding q is the last
-                // row whose start is <= q (starts do not decrease)
-                auto locate = [&](int32_t q) -> int64_t {
-                    int rr = 0;
-                    for (int step = 32; step >= 1; step >>= 1) {
-                        const int mid = rr + step;
-                        if (__shfl(start, mid, 64) <= q) rr = mid;
+                const int32_t total = __builtin_amdgcn_readlane(incl, 63);
+                // stream positions b .. b+63 -> slots, one per lane: of the
+                // non-empty rows that overlap them (a few; ascending, each
+                // starting where the previous one ends) each lane keeps the
+                // last one that starts at or before its position
+                const int32_t fs = first - start;
+                auto locate = [&](int32_t b) -> int32_t {
+                    const int32_t q = b + (int32_t)lane;
+                    int32_t d = 0;
+                    for (unsigned long long m = __ballot(len > 0 && start < b + 64 && incl > b); m;
+                         m &= m - 1) {
+                        const int j = __builtin_ctzll(m);
+                        const int32_t sj = __builtin_amdgcn_readlane(start, j);
+                        const int32_t dj = __builtin_amdgcn_readlane(fs, j);
+                        if (q >= sj) d = dj;
                     }
-                    return (int64_t)__shfl(first, rr, 64) + (q - __shfl(start, rr, 64));
+                    return q + d;
                 };
                 // candidates in chunks of kHold batches of 64, held in
                 // registers while each target of the run tests the whole
@@ -286,7 +323,7 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                         xk[k] = yk[k] = zk[k] = 0.0;
                         hk[k] = 0.f;
                         if (cb0 + 64 * k < total) {          // uniform
-                            tk[k] = (int32_t)locate(q);
+                            tk[k] = locate(cb0 + 64 * k);
                             if (vk[k]) {
                                 xk[k] = xs[tk[k]];
                                 yk[k] = ys[tk[k]];
@@ -325,7 +362,9 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                                 c += __builtin_popcountll(mask);
                             }
                         }
-                        if (lane == (unsigned)L) mine = c;
+                        // lane L's count := c (one lane written, whatever the
+                        // execution mask)
+                        asm volatile("v_writelane_b32 %0, %1, m0" : "+v"(mine) : "s"(c), "{m0}"(L));
                     }
                 }
             }
