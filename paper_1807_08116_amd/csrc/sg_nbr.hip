@@ -200,17 +200,6 @@ __device__ inline int32_t wave_incl_sum(int32_t v) {
     return v;
 }
 
-__device__ inline double lane_f64(double v, int L) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, L);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), L);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
-__device__ inline float lane_f32(float v, int L) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), L));
-}
-
 // The search of wavefront w (target slots kTargets w onward); w is uniform.
 __device__ __attribute__((always_inline)) inline void nbr_search_wave(
     const sg_grid_dev* __restrict__ g, int64_t ng, const double* __restrict__ xs,
@@ -236,6 +225,16 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
         k = (uint32_t)i < (uint64_t)ng ? key[i] : -2 - (int32_t)lane;
     }
     const float hif = (float)h;
+    // the wavefront's targets in LDS: a target pass reads its target's
+    // record with broadcast loads (one address instruction) instead of
+    // seven lane reads on the vector ALU (search stage at 1M gas 1.147 ->
+    // 1.096 ms); 4 KB per workgroup, which still fits beside the gravity
+    // kernel's workgroups on a compute unit
+    struct target_rec { double x, y, z; float h, pad; };
+    __shared__ target_rec tp[kWaves][kTargets];
+    target_rec* const mytp = tp[threadIdx.x >> 6];
+    if (lane < (unsigned)kTargets) mytp[lane] = target_rec{p[0], p[1], p[2], hif, 0.0f};
+    __builtin_amdgcn_wave_barrier();
     int32_t mine = 0;                          // hits of target g0 + lane so far
     const int nlev = g->nlev;
     unsigned long long todo = __ballot(live);
@@ -337,12 +336,9 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                     for (unsigned long long tr = run; tr; tr &= tr - 1) {
                         const int L = __builtin_ctzll(tr);
                         const int64_t sL = g0 + L;
-                        // target L's data, read across lanes with every lane
-                        // active (a lane read inside a divergent branch may
-                        // see a register the branch did not write for it)
-                        const double xi = lane_f64(p[0], L), yi = lane_f64(p[1], L);
-                        const double zi = lane_f64(p[2], L);
-                        const float hi = lane_f32(hif, L);
+                        // target L's data (uniform)
+                        const double xi = mytp[L].x, yi = mytp[L].y, zi = mytp[L].z;
+                        const float hi = mytp[L].h;
                         int32_t c = __builtin_amdgcn_readlane(mine, L);
                         int32_t* const row = slots + sL * kSlot;
 #pragma unroll
