@@ -92,19 +92,22 @@ constexpr int64_t kSlot = 96;              // scratch entries per target
 // R = (h + hmax_l)(1 + 2^-10) of p; false when the level has no such cell.
 __device__ inline bool level_box(const sg_grid_dev* __restrict__ g, int l, const double p[3],
                                  double h, int32_t lo[3], int32_t hi3[3]) {
-    const double R = (h + g->hmaxlev[l]) * (1.0 + 0x1p-10);
+    // in cell units: the reach R inv and the position (p - o) inv (their
+    // rounding differs from that of (p +- R - o) inv by far less than the
+    // 2^-10 margin of R, so the box still holds every cell within reach)
     const double inv = g->invL[l];
+    const double Ri = (h + g->hmaxlev[l]) * (1.0 + 0x1p-10) * inv;
     bool empty = false;
     for (int d = 0; d < 3; ++d) {
-        const double o = g->org[l][d];
-        const double top = (double)(g->dim[l][d] - 1);
-        double a = floor((p[d] - R - o) * inv);
-        double b = floor((p[d] + R - o) * inv);
-        if (b < 0.0 || a > top) empty = true;
-        a = a < 0.0 ? 0.0 : (a > top ? top : a);
-        b = b < 0.0 ? 0.0 : (b > top ? top : b);
-        lo[d] = (int32_t)a;                  // in [0, dim - 1]: cell indices fit int32
-        hi3[d] = (int32_t)b;
+        const double c = (p[d] - g->org[l][d]) * inv;
+        // clamped into [-1, 2^30] first, where the conversion is exact (a
+        // NaN becomes -1: an empty box)
+        const int32_t a = (int32_t)fmin(fmax(floor(c - Ri), -1.0), 0x1p30);
+        const int32_t b = (int32_t)fmin(fmax(floor(c + Ri), -1.0), 0x1p30);
+        const int32_t top = (int32_t)g->dim[l][d] - 1;
+        if (b < 0 || a > top) empty = true;
+        lo[d] = min(max(a, 0), top);
+        hi3[d] = min(max(b, 0), top);
     }
     return !empty;
 }
@@ -314,25 +317,32 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                     unsigned long long vm[kHold];          // lanes holding a candidate
                     double xk[kHold], yk[kHold], zk[kHold];
                     float hk[kHold];
+                    // every batch's loads are issued before any is used
+                    // (h converts to FP32 after the last one); lanes past
+                    // the stream load a clamped slot and are masked out
+                    double hd[kHold];
 #pragma unroll
                     for (int k = 0; k < kHold; ++k) {
                         const int32_t q = cb0 + 64 * k + (int32_t)lane;
                         vk[k] = q < total;
                         tk[k] = 0;
-                        xk[k] = yk[k] = zk[k] = 0.0;
-                        hk[k] = 0.f;
+                        xk[k] = yk[k] = zk[k] = hd[k] = 0.0;
                         if (cb0 + 64 * k < total) {          // uniform
                             tk[k] = locate(cb0 + 64 * k);
-                            if (vk[k]) {
-                                xk[k] = xs[tk[k]];
-                                yk[k] = ys[tk[k]];
-                                zk[k] = zs[tk[k]];
-                                hk[k] = (float)hs[tk[k]];
-                            }
+                            const int32_t t = min(max(tk[k], 0), (int32_t)(ng - 1));
+                            xk[k] = xs[t];
+                            yk[k] = ys[t];
+                            zk[k] = zs[t];
+                            hd[k] = hs[t];
                         }
                         const int32_t nk = total - (cb0 + 64 * k);
                         vm[k] = nk >= 64 ? ~0ull : (nk > 0 ? (1ull << nk) - 1 : 0ull);
                     }
+                    // (an empty statement that takes the loaded values keeps
+                    // the conversions, and their waits, behind the last load)
+                    asm volatile("" : "+v"(hd[0]), "+v"(hd[1]), "+v"(hd[2]), "+v"(hd[3]));
+#pragma unroll
+                    for (int k = 0; k < kHold; ++k) hk[k] = (float)hd[k];
                     for (unsigned long long tr = run; tr; tr &= tr - 1) {
                         const int L = __builtin_ctzll(tr);
                         const int64_t sL = g0 + L;
@@ -410,7 +420,17 @@ __device__ __attribute__((always_inline)) inline void nbr_compact_wave(
     if (c <= kSlot) {
         const int32_t* mine = slots + s * kSlot;
         const int64_t to = nbr_off[s < ng ? s : 0];
-        for (int64_t k = lane % kCompactLanes; k < c; k += kCompactLanes) nbr_idx[to + k] = mine[k];
+        // four entries in flight per lane, then the rest
+        int64_t k = lane % kCompactLanes;
+        for (; k + 3 * kCompactLanes < c; k += 4 * kCompactLanes) {
+            const int32_t v0 = mine[k], v1 = mine[k + kCompactLanes];
+            const int32_t v2 = mine[k + 2 * kCompactLanes], v3 = mine[k + 3 * kCompactLanes];
+            nbr_idx[to + k] = v0;
+            nbr_idx[to + k + kCompactLanes] = v1;
+            nbr_idx[to + k + 2 * kCompactLanes] = v2;
+            nbr_idx[to + k + 3 * kCompactLanes] = v3;
+        }
+        for (; k < c; k += kCompactLanes) nbr_idx[to + k] = mine[k];
     }
     for (int j = 0; j < kCompact; ++j) {
         const int64_t sj = s0 + j;
