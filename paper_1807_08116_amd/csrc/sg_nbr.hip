@@ -313,7 +313,7 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                 };
                 // candidates in chunks of kHold batches of 64, held in
                 // registers while each target of the run tests the whole
-                // chunk (its data read across lanes once per chunk, its hit
+                // chunk (its record read from LDS once per chunk, its hit
                 // count carried in a scalar register)
                 for (int32_t cb0 = 0; cb0 < total; cb0 += 64 * kHold) {
                     int32_t tk[kHold];
@@ -344,6 +344,7 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                     }
                     // (an empty statement that takes the loaded values keeps
                     // the conversions, and their waits, behind the last load)
+                    static_assert(kHold == 4, "the statement below names each held batch");
                     asm volatile("" : "+v"(hd[0]), "+v"(hd[1]), "+v"(hd[2]), "+v"(hd[3]));
 #pragma unroll
                     for (int k = 0; k < kHold; ++k) hk[k] = (float)hd[k];
