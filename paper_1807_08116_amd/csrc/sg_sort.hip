@@ -14,20 +14,37 @@ constexpr int kBlock = 256;
 
 __device__ inline unsigned lane_id() { return threadIdx.x & 63; }
 
-__device__ inline unsigned long long wave_min_u64(unsigned long long v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
+// 64-bit minimum and maximum over the 64 lanes by DPP row operations on the
+// two 32-bit halves, with no chain of shuffles through LDS (h minimum,
+// Morton box, equal-key runs of the key pass).  Every lane must be active;
+// the result is uniform.  Controls: quad_perm
+// [1,0,3,2] 0xb1, [2,3,0,1] 0x4e, row_half_mirror 0x141, row_mirror 0x140,
+// row_bcast:15 0x142 (lane 15 of each row into the next row), row_bcast:31
+// 0x143 (lane 31 into rows 2 and 3).
+template <int kCtrl, int kRowMask = 0xf>
+__device__ inline unsigned long long dpp_u64(unsigned long long old, unsigned long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)old, (int)(unsigned)v,
+                                                              kCtrl, kRowMask, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(
+        (int)(unsigned)(old >> 32), (int)(unsigned)(v >> 32), kCtrl, kRowMask, 0xf, false);
+    return ((unsigned long long)hi << 32) | lo;
 }
-__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
+template <bool kMax>
+__device__ inline unsigned long long wave_ext_u64(unsigned long long v) {
+    constexpr unsigned long long I = kMax ? 0ull : ~0ull;
+    auto pick = [](unsigned long long a, unsigned long long b) { return (kMax ? b > a : b < a) ? b : a; };
+    v = pick(v, dpp_u64<0xb1>(I, v));
+    v = pick(v, dpp_u64<0x4e>(I, v));
+    v = pick(v, dpp_u64<0x141>(I, v));
+    v = pick(v, dpp_u64<0x140>(I, v));          // each row of 16: its extreme
+    v = pick(v, dpp_u64<0x142, 0xa>(I, v));     // rows 1, 3: with rows 0, 2
+    v = pick(v, dpp_u64<0x143, 0xc>(I, v));     // rows 2, 3: with rows 0, 1
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
 }
+__device__ inline unsigned long long wave_min_u64(unsigned long long v) { return wave_ext_u64<false>(v); }
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) { return wave_ext_u64<true>(v); }
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -289,27 +306,18 @@ __device__ inline void grid_levels_block(const double* __restrict__ x,
                 valid = false;
             }
         }
-        unsigned long long rem = __ballot(valid);
-        while (rem) {
-            int leader = __builtin_ctzll(rem);
-            int L = __shfl(lev, leader, 64);
-            bool mine = valid && lev == L;
-            unsigned long long mm = __ballot(mine);
+        // one LDS atomic per bound and particle: a wavefront's particles
+        // arrive in input order and spread over several levels, and seven
+        // wavefront reductions per level present had cost more (sort stage
+        // at 1M gas 0.427 ms with shuffle reductions, 0.408 with DPP ones,
+        // 0.384 with these atomics)
+        if (valid) {
             for (int d = 0; d < 3; ++d) {
-                unsigned long long o = mine ? sg_ord(p[d]) : ~0ull;
-                unsigned long long mnv = wave_min_u64(o);
-                unsigned long long mxv = wave_max_u64(mine ? sg_ord(p[d]) : 0ull);
-                if ((int)lane_id() == leader) {
-                    atomicMin(&s_lo[L][d], mnv);
-                    atomicMax(&s_hi[L][d], mxv);
-                }
+                atomicMin(&s_lo[lev][d], sg_ord(p[d]));
+                atomicMax(&s_hi[lev][d], sg_ord(p[d]));
             }
-            unsigned long long hm = wave_max_u64(mine ? sg_ord(hi) : 0ull);
-            if ((int)lane_id() == leader) {
-                atomicMax(&s_hmax[L], hm);
-                atomicAdd(&s_cnt[L], (unsigned long long)__builtin_popcountll(mm));
-            }
-            rem &= ~mm;
+            atomicMax(&s_hmax[lev], sg_ord(hi));
+            atomicAdd(&s_cnt[lev], 1ull);
         }
     }
     if (bad) atomicOr(&g->err, SGE_LEVELS);
