@@ -41,7 +41,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 // Targets per wavefront of the search (lanes 0 .. kTargets-1 hold them;
 // all 64 lanes hold candidates).  The search is bound by the vector-ALU
-// work of its pair tests (busy over 90 % of the kernel at 2M particles),
+// work of its pair tests (busy 85 % of the kernel at 2M particles),
 // and the wavefronts' work varies widely (runs of 1 to 64 targets, union
 // boxes over 1 to 5 levels), so shorter wavefronts pack the SIMDs better
 // at the end of the launch: the search stage took 1.62 ms with 64 targets
@@ -50,10 +50,11 @@ constexpr int kWaves = kBlock / 64;
 // the set-up as it is now, 0.98-0.99, 0.96-0.97 and 1.00 ms.
 constexpr int kTargets = 32;
 // Candidate batches held in registers per target pass: each target's data
-// is read and its hit count fetched once per kHold batches
-// instead of once per batch (about 23 instead of 28 vector instructions per
-// 64 pair tests).  Search stage at 2M particles: 1.53 ms with one batch,
-// 1.41 with 2, 1.32 with 4, 1.49 with 8 (113 VGPRs: 4 waves per SIMD).
+// is read and its hit count fetched once per kHold batches instead of once
+// per batch.  Search stage at 2M particles when the target data were lane
+// reads (about 23 instead of 28 vector instructions per 64 pair tests):
+// 1.53 ms with one batch, 1.41 with 2, 1.32 with 4, 1.49 with 8 (113 VGPRs:
+// 4 waves per SIMD).
 constexpr int kHold = 4;
 
 __device__ inline unsigned rank_below(unsigned long long mask) {
