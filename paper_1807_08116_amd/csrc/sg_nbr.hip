@@ -14,7 +14,7 @@
 // target slots and walks them cell by cell: the targets that share a cell
 // key form a run, and the run's search region is the union (per level) of
 // its targets' boxes.  The rows of that region are flattened into one
-// candidate stream, loaded 256 candidates at a time (four per lane) and
+// candidate stream, loaded 192 candidates at a time (three per lane) and
 // held in registers while every target of the run tests them, so a
 // candidate is fetched once per cell instead of once per target.  Any
 // grouping gives the same lists: the union contains each target's own box,
@@ -54,8 +54,9 @@ constexpr int kTargets = 32;
 // per batch.  Search stage at 2M particles when the target data were lane
 // reads (about 23 instead of 28 vector instructions per 64 pair tests):
 // 1.53 ms with one batch, 1.41 with 2, 1.32 with 4, 1.49 with 8 (113 VGPRs:
-// 4 waves per SIMD).
-constexpr int kHold = 4;
+// 4 waves per SIMD).  With the set-up as it is now: 2: 0.98-0.99 ms, 3:
+// 0.94 (63 VGPRs), 4: 0.96, 6: 1.01-1.02.
+constexpr int kHold = 3;
 
 __device__ inline unsigned rank_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
@@ -345,8 +346,8 @@ __device__ __attribute__((always_inline)) inline void nbr_search_wave(
                     }
                     // (an empty statement that takes the loaded values keeps
                     // the conversions, and their waits, behind the last load)
-                    static_assert(kHold == 4, "the statement below names each held batch");
-                    asm volatile("" : "+v"(hd[0]), "+v"(hd[1]), "+v"(hd[2]), "+v"(hd[3]));
+                    static_assert(kHold == 3, "the statement below names each held batch");
+                    asm volatile("" : "+v"(hd[0]), "+v"(hd[1]), "+v"(hd[2]));
 #pragma unroll
                     for (int k = 0; k < kHold; ++k) hk[k] = (float)hd[k];
                     for (unsigned long long tr = run; tr; tr &= tr - 1) {
