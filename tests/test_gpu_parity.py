@@ -324,6 +324,69 @@ def test_block_order_boundaries(sg, orc, ng):
         assert e_rho < tol and e_acc < tol
 
 
+# A dense core of small-h gas with a few large-h gas particles inside it and
+# a separate medium-h cluster far away: six levels, one of them empty.  The
+# large-h targets' boxes at the finest level span hundreds of rows (several
+# row chunks of the search's stream) and their rows overflow the search's
+# 96-entry slots; runs in the far cluster reach only some levels, and many
+# boxes hold no particle.
+def _mixed_state(rng):
+    core, big, far, nh = 3000, 40, 1000, 500
+    ng = core + big + far
+    pos = np.concatenate([rng.normal(scale=0.3, size=(core, 3)),
+                          rng.normal(scale=0.3, size=(big, 3)),
+                          rng.normal(scale=0.5, size=(far, 3)) + np.array([8.0, 0.0, 0.0]),
+                          rng.normal(scale=2.0, size=(nh, 3))])
+    h = np.concatenate([rng.uniform(0.03, 0.05, core), rng.uniform(0.6, 1.0, big),
+                        rng.uniform(0.15, 0.25, far)])
+    n = ng + nh
+    return {"ng": ng, "x": pos[:, 0].copy(), "y": pos[:, 1].copy(), "z": pos[:, 2].copy(),
+            "vx": rng.normal(size=n) * 0.1, "vy": rng.normal(size=n) * 0.1,
+            "vz": rng.normal(size=n) * 0.1, "m": rng.uniform(0.5, 1.5, n) / n,
+            "e": rng.uniform(0.02, 0.08, ng), "h": h}
+
+
+def _max_box_rows(orc, st, s):
+    """Largest (y, z) row count of one target's search box over the levels."""
+    ng = st["ng"]
+    g = orc.grid_dict(s["grid"])
+    h = st["h"]
+    best = 0
+    for l in range(g["nlev"]):
+        if g["ncell"][l] == 0:
+            continue
+        R = (h + g["hmax"][l]) * (1 + 2.0 ** -10)
+        span = []
+        for d, p in ((1, st["y"][:ng]), (2, st["z"][:ng])):
+            o, top = g["org"][l][d], g["dim"][l][d] - 1
+            a = np.clip(np.floor((p - R - o) / g["L"][l]), 0, top)
+            b = np.clip(np.floor((p + R - o) / g["L"][l]), 0, top)
+            span.append(b - a + 1)
+        best = max(best, int((span[0] * span[1]).max()))
+    return best
+
+
+def test_mixed_level_neighbourhoods(sg, orc):
+    from paper_1807_08116_amd import ic
+    st = _mixed_state(np.random.default_rng(1807))
+    ng = st["ng"]
+    s, nb, soff, sidx = oracle_sort_and_rows(orc, st)
+    # the case reaches the paths it is meant for
+    assert _max_box_rows(orc, st, s) > 64
+    assert int(np.diff(soff).max()) > 96
+    assert 0 in orc.grid_dict(s["grid"])["ncell"]
+    ref = orc.forces(st, ic.DEFAULT_PARAMS)
+    A = oracle_accel(orc, st, ref)
+    for prec, tol in ((sg.SG_FP64, FP64_TOL), (sg.SG_FP32C, FP32C_TOL)):
+        eng = sg.Engine(st, precision=prec)
+        full_eval(eng, sg)
+        check_sort_bitexact(sg, eng, s, soff, sidx, orc)
+        e_rho = nrm_err(eng.numpy("rho")[:ng], ref["rho"])
+        e_acc = nrm_err(gpu_accel(eng), A)
+        print("mixed levels", prec, "nnz", len(sidx), "rho %.2e acc %.2e" % (e_rho, e_acc))
+        assert e_rho < tol and e_acc < tol
+
+
 def test_capacity_overflow_and_retry(sg, orc, c0, c0_ref):
     ref, s, soff, sidx = c0_ref
     caps = sg.default_caps(c0["ng"], len(c0["x"]) - c0["ng"], cell_cap=10, nnz_cap=100)
